@@ -1,0 +1,205 @@
+/*
+ * spde.h -- C interface of the MI355X (gfx950) SPDE field sampler.
+ *
+ * The library draws Gaussian random fields with exponential (Matern nu = 1/2)
+ * covariance by the method of Osborn et al., "Scalable hierarchical PDE
+ * sampler for generating spatially correlated random fields using
+ * non-matching meshes" (arXiv:1712.06758):
+ *
+ *   1. the reaction-diffusion SPDE (kappa^2 - Laplacian) u = g W is discretised
+ *      with lowest-order Raviart-Thomas fluxes and piecewise-constant cells on
+ *      a structured box with sigma.n = 0 on the boundary (Sec. "Mixed finite
+ *      element discretization", eq. reac_diff_weak), giving the saddle-point
+ *      system eq. linsys / linsys_blocks
+ *         [M  B^T       ] [sigma]   [ 0                 ]
+ *         [B  -kappa^2 W] [u    ] = [ -g W^{1/2} xi     ],  xi ~ N(0, I);
+ *   2. that system is solved with block-preconditioned MINRES whose
+ *      preconditioner is blkdiag(diag(M), V), V one geometric-multigrid V-cycle
+ *      on the approximate Schur complement kappa^2 W + B diag(M)^-1 B^T
+ *      (the approximate Schur complement of eq. ldu with the kappa^2 W term);
+ *   3. the cell field is projected onto a non-matching tetrahedral mesh,
+ *      u_tet = Pi u, Pi = W_h^-1 G (Sec. "L2-Projection", eq. proj_op);
+ *   4. coarse samples of the same event use the restricted noise of
+ *      eq. ml-linsys (F_{l+1} = P^T F_l).
+ *
+ * Geometry and ordering
+ *   The box is the unit cube [0,1]^3 with n^3 cubic cells, h = 1/n.
+ *   Cells:  c = i + n*(j + n*k)                       (x fastest)
+ *   Faces (external arrays, 3 n^2 (n+1) entries per sample):
+ *           x-faces  i + (n+1)*(j + n*k),              i in 0..n
+ *           y-faces  n^2(n+1) + i + n*(j + (n+1)*k),   j in 0..n
+ *           z-faces  2 n^2(n+1) + i + n*(j + n*k),     k in 0..n
+ *   A face value is the normal flux component along +x, +y or +z.
+ *   Boundary faces carry sigma.n = 0 and are written as 0.
+ *
+ * Memory
+ *   Pointers named *_dev are device pointers, *_host host pointers.  All
+ *   device memory is owned by the caller; the library never allocates device
+ *   memory.  It allocates a small pinned host buffer per context for the
+ *   convergence poll.
+ *
+ * Errors
+ *   Every entry point returns spde_status.  No exception crosses the
+ *   interface.  spde_last_error() gives a thread-local description of the
+ *   last non-OK status.  Handles are not thread-safe: use one handle per host
+ *   thread at a time.
+ */
+#ifndef SPDE_H
+#define SPDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spde_ctx* spde_handle;
+
+typedef enum {
+    SPDE_OK       = 0,   /* success                                                   */
+    SPDE_ENOTCONV = 1,   /* max_iter reached for some sample; all outputs are written */
+    SPDE_EINVAL   = -1,  /* invalid argument (size, range, null pointer, order)       */
+    SPDE_ENOMEM   = -2,  /* bound workspace too small for the request                 */
+    SPDE_EHIP     = -3,  /* a HIP runtime call failed                                 */
+    SPDE_EFAILED  = -4   /* breakdown or non-finite value in some sample: that
+                            sample's outputs are NaN, the others are valid           */
+} spde_status;
+
+typedef enum {
+    SPDE_FP64  = 0,      /* everything in float64                                     */
+    SPDE_MIXED = 1       /* float32 multigrid preconditioner inside float64 MINRES;
+                            residuals, inner products, recurrences, transfer in f64  */
+} spde_precision;
+
+/* ---- set-up ------------------------------------------------------------ */
+
+/* Create a sampler for the unit box with n^3 cells and SPDE coefficients
+ * kappa, g (Sec. "Mixed finite element discretization"; for unit marginal
+ * variance with nu = 1/2 in 3-D, g^2 = 8 pi kappa).
+ * n must be a power of two with 4 <= n <= 1024; kappa > 0; g > 0.
+ * Host-only: touches no GPU.  *out receives the handle (NULL on error). */
+spde_status spde_setup_box(int n, double kappa, double g, spde_handle* out);
+
+/* Choose precision, MINRES relative tolerance (on the preconditioned residual
+ * norm, from a zero initial guess), iteration cap and the largest batch.
+ * rtol in (0, 1); 1 <= max_iter <= 100000; 1 <= max_batch <= 4096.
+ * Invalidates any bound workspace.  Host-only. */
+spde_status spde_configure(spde_handle h, spde_precision prec, double rtol,
+                           int max_iter, int max_batch);
+
+/* Device workspace size in bytes needed by the current configuration. */
+size_t spde_workspace_bytes(spde_handle h);
+
+/* Bind a caller-owned device buffer of at least spde_workspace_bytes() bytes,
+ * 256-byte aligned.  The buffer must outlive every call that uses the handle.
+ * Selects the current HIP device as the handle's device. */
+spde_status spde_bind_workspace(spde_handle h, void* dev_ptr, size_t bytes);
+
+/* ---- L2 projection onto a tetrahedral mesh (Sec. "L2-Projection") ------- */
+
+/* Build Pi = W_h^-1 G on the host for a tet mesh lying inside [0,1]^3:
+ * Pi[t, c] = vol(tet t intersect cell c) / vol(tet t), exact overlap volumes
+ * by convex clipping (eq. proj_op with P0 spaces on both meshes).
+ *   xyz_host  [n_vert][3] float64 vertex coordinates
+ *   tet_host  [n_tet][4]  int32 vertex indices
+ * Outputs a CSR matrix in host memory allocated by the library:
+ *   *row_ptr_host [n_tet+1] int64, *col_host [nnz] int32 (ascending per row),
+ *   *val_host [nnz] float64; release each with spde_free_host().
+ * Returns SPDE_EINVAL for a vertex outside [0,1]^3, a degenerate tet or an
+ * index out of range.  Host-only; uses all OpenMP threads. */
+spde_status spde_build_transfer(spde_handle h, int64_t n_vert, const double* xyz_host,
+                                int64_t n_tet, const int32_t* tet_host,
+                                int64_t** row_ptr_host, int32_t** col_host,
+                                double** val_host, int64_t* nnz);
+
+/* Register a device copy of Pi (CSR as produced above).  The arrays are
+ * borrowed, not copied: they must stay valid while the handle samples. */
+spde_status spde_set_transfer(spde_handle h, int64_t n_tet, int64_t nnz,
+                              const int64_t* row_ptr_dev, const int32_t* col_dev,
+                              const double* val_dev);
+
+/* ---- the sampler --------------------------------------------------------- */
+
+/* Draw `batch` field samples from the noise vectors xi_dev [batch][n^3]:
+ * solve eq. linsys for each right-hand side, then project.
+ *   u_tet_dev  [batch][n_tet]      Pi u            (nullable if no transfer set)
+ *   u_box_dev  [batch][n^3]        box cell field  (nullable)
+ *   sigma_dev  [batch][3n^2(n+1)]  flux sigma = -M^-1 B^T u (nullable)
+ *   stream     hipStream_t to run on (NULL = default stream)
+ *   iters_host [batch] MINRES iterations per sample (nullable)
+ *   relres_host[batch] true relative residual ||F - A U|| / ||F|| with the
+ *              flux recovered from u (nullable; computing it costs one extra
+ *              pass, so NULL skips it unless sigma_dev is requested)
+ * Blocks the host until the solve has converged (it polls per-sample
+ * convergence flags every few iterations); the projection and the optional
+ * outputs are enqueued on `stream` before returning.  Samples are
+ * independent: each result is bitwise the same alone or in any batch.
+ * Returns SPDE_ENOTCONV if some sample hit max_iter (outputs written),
+ * SPDE_EFAILED on breakdown, SPDE_ENOMEM if batch > max_batch. */
+spde_status spde_sample(spde_handle h, int batch, const double* xi_dev,
+                        double* u_tet_dev, double* u_box_dev, double* sigma_dev,
+                        void* stream, int* iters_host, double* relres_host);
+
+/* Noise of the coupled coarse sample (eq. ml-linsys, F_{l+1} = P^T F_l):
+ * xi_c[I] = 8^{-1/2} * sum of xi_f over the 8 children of coarse cell I.
+ *   xi_f_dev [batch][n_fine^3] -> xi_c_dev [batch][(n_fine/2)^3]
+ * n_fine even and >= 2.  Asynchronous on `stream`. */
+spde_status spde_restrict_noise(int n_fine, int batch, const double* xi_f_dev,
+                                double* xi_c_dev, void* stream);
+
+/* ---- operators exposed for verification -------------------------------- */
+
+/* y = A x with A the saddle-point matrix of eq. linsys_blocks on the full
+ * external face/cell layout (boundary face entries of x are ignored, of y
+ * written as 0).  x_sigma/y_sigma [batch][3n^2(n+1)], x_u/y_u [batch][n^3].
+ * Needs a bound workspace; batch <= max_batch.  Asynchronous on `stream`. */
+spde_status spde_apply_operator(spde_handle h, int batch, const double* x_sigma_dev,
+                                const double* x_u_dev, double* y_sigma_dev,
+                                double* y_u_dev, void* stream);
+
+/* z = V r: one V-cycle of the configured precision on the approximate Schur
+ * complement (the u-block of the preconditioner).  r, z [batch][n^3].
+ * Asynchronous on `stream`. */
+spde_status spde_apply_vcycle(spde_handle h, int batch, const double* r_dev,
+                              double* z_dev, void* stream);
+
+/* u_tet = Pi u_box with the registered transfer.  [batch][n^3] -> [batch][n_tet].
+ * Asynchronous on `stream`. */
+spde_status spde_apply_transfer(spde_handle h, int batch, const double* u_box_dev,
+                                double* u_tet_dev, void* stream);
+
+/* ---- execution options and instrumentation ----------------------------- */
+
+/* Replay MINRES iterations from captured HIP graphs (1, default) or launch
+ * kernels one by one (0).  Results are bitwise identical either way. */
+spde_status spde_set_graphs(spde_handle h, int enable);
+
+/* Iterations per convergence poll (default 8; 1..256). */
+spde_status spde_set_poll_interval(spde_handle h, int iters);
+
+/* Per-kernel timing with HIP events on the sampling stream.  While enabled,
+ * kernels are launched one by one (no graphs) with an event pair around each
+ * launch of the named kernel classes; accumulated times are read with
+ * spde_timing_get().  enable = 0 stops and keeps the totals; -1 clears. */
+spde_status spde_timing(spde_handle h, int enable);
+int         spde_kernel_count(void);
+const char* spde_kernel_name(int id);
+spde_status spde_timing_get(spde_handle h, int id, double* total_ms, int64_t* launches,
+                            double* bytes_per_launch);
+
+/* Number of multigrid levels and the box edge of the coarsest level handled
+ * by per-level kernels (levels below it run in one persistent launch). */
+spde_status spde_info(spde_handle h, int* levels, int* persistent_top_n,
+                      int* device_lds_bytes);
+
+/* ---- teardown ------------------------------------------------------------ */
+
+void        spde_free_host(void* p);
+void        spde_destroy(spde_handle h);
+const char* spde_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPDE_H */

@@ -1,0 +1,254 @@
+"""MI355X (gfx950) SPDE Gaussian-field sampler: Python binding of libspde.
+
+The sampler follows Osborn et al., "Scalable hierarchical PDE sampler for
+generating spatially correlated random fields using non-matching meshes"
+(arXiv:1712.06758): white noise xi -> RT0/P0 mixed solve of
+(kappa^2 - Laplacian) u = g W on a structured box (eq. linsys) -> L2
+projection onto a tet mesh (eq. proj_op).  Every step runs in the HIP kernels
+of ``_lib/libspde.so``; this module only marshals arguments.  PyTorch supplies
+device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+
+from . import _abi
+from ._abi import SpdeError, SPDE_FP64, SPDE_MIXED, SPDE_OK, SPDE_ENOTCONV, SPDE_EFAILED  # noqa: F401
+
+__all__ = ["Box", "restrict_noise", "g_unit_variance", "SpdeError", "build_transfer_host",
+           "kernel_names", "SPDE_FP64", "SPDE_MIXED"]
+
+
+def g_unit_variance(kappa: float) -> float:
+    """g with unit marginal variance for nu = 1/2 in 3-D: g^2 = 8 pi kappa."""
+    return math.sqrt(8.0 * math.pi * kappa)
+
+
+def kernel_names():
+    L = _abi.lib()
+    return [L.spde_kernel_name(i).decode() for i in range(L.spde_kernel_count())]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(device):
+    torch = _torch()
+    s = torch.cuda.current_stream(device).cuda_stream
+    return C.c_void_p(s) if s else None
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_dev_f64(t, shape, name):
+    torch = _torch()
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class _Handle:
+    """Owns one spde_handle (host side only)."""
+
+    def __init__(self, n, kappa, g):
+        h = C.c_void_p()
+        _abi.check(_abi.lib().spde_setup_box(int(n), float(kappa), float(g), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _abi._lib is not None:
+            _abi._lib.spde_destroy(self.h)
+            self.h = None
+
+
+def build_transfer_host(n: int, xyz: np.ndarray, tets: np.ndarray):
+    """Pi = W_h^-1 G for a tet mesh inside [0,1]^3, built by the library's host
+    clipper.  Returns (row_ptr int64, cols int32, vals float64) numpy arrays."""
+    L = _abi.lib()
+    hh = _Handle(n, 1.0, 1.0)
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    rp = C.POINTER(C.c_int64)()
+    ci = C.POINTER(C.c_int32)()
+    cv = C.POINTER(C.c_double)()
+    nnz = C.c_int64()
+    _abi.check(L.spde_build_transfer(hh.h, xyz.shape[0], xyz.ctypes.data, tets.shape[0], tets.ctypes.data,
+                                     C.byref(rp), C.byref(ci), C.byref(cv), C.byref(nnz)))
+    try:
+        nt = tets.shape[0]
+        row_ptr = np.ctypeslib.as_array(rp, shape=(nt + 1,)).copy()
+        cols = np.ctypeslib.as_array(ci, shape=(max(1, nnz.value),))[:nnz.value].copy()
+        vals = np.ctypeslib.as_array(cv, shape=(max(1, nnz.value),))[:nnz.value].copy()
+    finally:
+        L.spde_free_host(C.cast(rp, C.c_void_p))
+        L.spde_free_host(C.cast(ci, C.c_void_p))
+        L.spde_free_host(C.cast(cv, C.c_void_p))
+    return row_ptr, cols, vals
+
+
+def restrict_noise(xi_f, n_fine: int):
+    """Noise of the coupled coarse sample: [B, n^3] -> [B, (n/2)^3] on the device."""
+    torch = _torch()
+    B = xi_f.shape[0]
+    _check_dev_f64(xi_f, (B, n_fine ** 3), "xi_f")
+    out = torch.empty((B, (n_fine // 2) ** 3), dtype=torch.float64, device=xi_f.device)
+    with torch.cuda.device(xi_f.device):
+        _abi.check(_abi.lib().spde_restrict_noise(n_fine, B, _ptr(xi_f), _ptr(out), _stream_ptr(xi_f.device)))
+    return out
+
+
+class Box:
+    """A resident sampler for the n^3 unit box.
+
+    precision: "fp64" (everything float64) or "mixed" (float32 multigrid
+    preconditioner inside float64 MINRES).  rtol is MINRES's relative
+    tolerance on the preconditioned residual norm.
+    """
+
+    def __init__(self, n: int, kappa: float, g: float | None = None, precision: str = "fp64",
+                 rtol: float | None = None, max_iter: int = 1000, max_batch: int = 1, device=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the SPDE sampler needs a GPU (torch.cuda.is_available() is False)")
+        self.n = int(n)
+        self.kappa = float(kappa)
+        self.g = float(g) if g is not None else g_unit_variance(kappa)
+        self.precision = precision
+        prec = {"fp64": SPDE_FP64, "mixed": SPDE_MIXED}[precision]
+        if rtol is None:
+            rtol = 3e-11 if precision == "fp64" else 1e-8
+        self.rtol = float(rtol)
+        self.max_batch = int(max_batch)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._hh = _Handle(self.n, self.kappa, self.g)
+        L = _abi.lib()
+        _abi.check(L.spde_configure(self._hh.h, prec, self.rtol, int(max_iter), self.max_batch))
+        nbytes = L.spde_workspace_bytes(self._hh.h)
+        with torch.cuda.device(self.device):
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            _abi.check(L.spde_bind_workspace(self._hh.h, _ptr(self._ws), nbytes))
+        self.n_tet = 0
+        self._pi = None
+
+    # -- transfer ---------------------------------------------------------
+    def set_mesh(self, xyz: np.ndarray, tets: np.ndarray):
+        """Build Pi for the tet mesh on the host and keep a device copy."""
+        rp, ci, cv = build_transfer_host(self.n, xyz, tets)
+        return self.set_transfer(rp, ci, cv)
+
+    def set_transfer(self, row_ptr, cols, vals):
+        torch = _torch()
+        d = self.device
+        rp = torch.as_tensor(np.asarray(row_ptr, dtype=np.int64)).to(d)
+        ci = torch.as_tensor(np.asarray(cols, dtype=np.int32)).to(d)
+        cv = torch.as_tensor(np.asarray(vals, dtype=np.float64)).to(d)
+        self._pi = (rp, ci, cv)
+        self.n_tet = rp.numel() - 1
+        self.nnz = ci.numel()
+        _abi.check(_abi.lib().spde_set_transfer(self._hh.h, self.n_tet, self.nnz, _ptr(rp), _ptr(ci), _ptr(cv)))
+        return self.n_tet, self.nnz
+
+    # -- sampling ---------------------------------------------------------
+    def sample(self, xi, u_tet=True, u_box=False, sigma=False, relres=False, allow_notconv=False):
+        """Fields for the noise batch xi [B, n^3] (float64, on the device).
+
+        Returns a dict with "u_tet" [B, n_tet] (if a mesh is set and u_tet),
+        "u_box" [B, n^3], "sigma" [B, 3 n^2 (n+1)], "iters" (numpy int32 [B]),
+        "relres" (numpy float64 [B]) and "status"."""
+        torch = _torch()
+        B = xi.shape[0]
+        nc = self.n ** 3
+        _check_dev_f64(xi, (B, nc), "xi")
+        out = {}
+        kw = dict(dtype=torch.float64, device=self.device)
+        t_tet = torch.empty((B, self.n_tet), **kw) if (u_tet and self.n_tet) else None
+        t_box = torch.empty((B, nc), **kw) if u_box else None
+        t_sig = torch.empty((B, 3 * self.n * self.n * (self.n + 1)), **kw) if sigma else None
+        iters = np.zeros(B, dtype=np.int32)
+        rel = np.zeros(B, dtype=np.float64) if relres else None
+        with torch.cuda.device(self.device):
+            st = self._hh and _abi.lib().spde_sample(
+                self._hh.h, B, _ptr(xi), _ptr(t_tet), _ptr(t_box), _ptr(t_sig), _stream_ptr(self.device),
+                iters.ctypes.data_as(C.c_void_p),
+                rel.ctypes.data_as(C.c_void_p) if rel is not None else None)
+        allow = (SPDE_OK, SPDE_ENOTCONV) if allow_notconv else (SPDE_OK,)
+        _abi.check(st, allow)
+        out["status"] = st
+        if t_tet is not None:
+            out["u_tet"] = t_tet
+        if t_box is not None:
+            out["u_box"] = t_box
+        if t_sig is not None:
+            out["sigma"] = t_sig
+        out["iters"] = iters
+        if rel is not None:
+            out["relres"] = rel
+        return out
+
+    # -- operators exposed for verification ------------------------------
+    def apply_operator(self, x_sigma, x_u):
+        torch = _torch()
+        B = x_u.shape[0]
+        nf = 3 * self.n * self.n * (self.n + 1)
+        _check_dev_f64(x_sigma, (B, nf), "x_sigma")
+        _check_dev_f64(x_u, (B, self.n ** 3), "x_u")
+        ys = torch.empty_like(x_sigma)
+        yu = torch.empty_like(x_u)
+        with torch.cuda.device(self.device):
+            _abi.check(_abi.lib().spde_apply_operator(self._hh.h, B, _ptr(x_sigma), _ptr(x_u), _ptr(ys), _ptr(yu),
+                                                      _stream_ptr(self.device)))
+        return ys, yu
+
+    def apply_vcycle(self, r):
+        torch = _torch()
+        B = r.shape[0]
+        _check_dev_f64(r, (B, self.n ** 3), "r")
+        z = torch.empty_like(r)
+        with torch.cuda.device(self.device):
+            _abi.check(_abi.lib().spde_apply_vcycle(self._hh.h, B, _ptr(r), _ptr(z), _stream_ptr(self.device)))
+        return z
+
+    def apply_transfer(self, u_box):
+        torch = _torch()
+        B = u_box.shape[0]
+        _check_dev_f64(u_box, (B, self.n ** 3), "u_box")
+        out = torch.empty((B, self.n_tet), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _abi.check(_abi.lib().spde_apply_transfer(self._hh.h, B, _ptr(u_box), _ptr(out),
+                                                      _stream_ptr(self.device)))
+        return out
+
+    # -- execution options / instrumentation ------------------------------
+    def set_graphs(self, enable: bool):
+        _abi.check(_abi.lib().spde_set_graphs(self._hh.h, int(bool(enable))))
+
+    def set_poll_interval(self, k: int):
+        _abi.check(_abi.lib().spde_set_poll_interval(self._hh.h, int(k)))
+
+    def timing(self, mode: int):
+        _abi.check(_abi.lib().spde_timing(self._hh.h, int(mode)))
+
+    def timing_report(self):
+        L = _abi.lib()
+        rep = {}
+        for i in range(L.spde_kernel_count()):
+            ms = C.c_double(); cnt = C.c_int64(); bpl = C.c_double()
+            _abi.check(L.spde_timing_get(self._hh.h, i, C.byref(ms), C.byref(cnt), C.byref(bpl)))
+            if cnt.value:
+                rep[L.spde_kernel_name(i).decode()] = {"total_ms": ms.value, "launches": cnt.value,
+                                                       "bytes_per_launch": bpl.value}
+        return rep
+
+    def info(self):
+        lv = C.c_int(); top = C.c_int(); lds = C.c_int()
+        _abi.check(_abi.lib().spde_info(self._hh.h, C.byref(lv), C.byref(top), C.byref(lds)))
+        return {"levels": lv.value, "persistent_top_n": top.value, "device_lds_bytes": lds.value,
+                "workspace_bytes": self._ws.numel()}

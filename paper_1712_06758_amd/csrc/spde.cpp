@@ -1,0 +1,697 @@
+// C interface and host orchestration of the SPDE field sampler.
+//
+// The solve of eq. linsys for a batch of noise vectors runs as a loop of
+// MINRES iterations on the device; the host only replays iteration blocks
+// (captured HIP graphs, or plain launches) and polls per-sample convergence
+// flags between blocks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/spde.h"
+#include "spde_internal.h"
+
+namespace spde {
+int build_transfer_csr(int n, int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tets,
+                       std::vector<int64_t>& row_ptr, std::vector<int32_t>& cols, std::vector<double>& vals,
+                       char* err, size_t errlen);
+}
+
+using namespace spde;
+
+namespace {
+
+thread_local std::string g_err;
+
+spde_status fail(spde_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+spde_status fail(spde_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail(SPDE_EHIP, "%s: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+  } while (0)
+
+const char* kKernelNames[KID_COUNT] = {
+    "init", "mg_down_fine", "mg_down", "mg_coarse", "mg_up", "mg_up_fine",
+    "scalar", "operator", "output", "flux", "resid", "spmm", "restrict_noise"};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+namespace spde {
+
+struct LaunchRec {
+  int kid;
+  int iter;          // MINRES iteration of the launch (0 outside the loop)
+  int level;         // multigrid level of a level kernel
+  hipEvent_t e0, e1;
+};
+
+struct Ctx {
+  // problem
+  int n = 0;
+  double kappa = 0, g = 0;
+  Box box{};
+  // configuration
+  int prec = SPDE_FP64;
+  double rtol = 1e-10;
+  int max_iter = 1000;
+  int max_batch = 1;
+  bool configured = false;
+  // hierarchy
+  int nlev = 0;                 // levels 0..nlev-1 (m = n >> l, down to 1)
+  Level lv[kMaxLevels];
+  int top = 1;                  // first level handled by the persistent kernel
+  size_t coarse_lds = 0;
+  CoarseParams cp{};
+  int shape_down[kMaxLevels];
+  int shape_up[kMaxLevels];
+  int nb_up0 = 0, nb_pb = 0;
+  // device
+  int device = -1;
+  int lds_limit = 65536;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Fields F{};
+  void* mgb[kMaxLevels] = {};   // restricted right-hand sides per level (l >= 1)
+  void* mge[kMaxLevels] = {};   // level corrections (l >= 1)
+  double* resid_out = nullptr;  // [max_batch]
+  hipStream_t own_stream = nullptr;
+  Scalars* host_sc = nullptr;   // pinned
+  double* host_res = nullptr;   // pinned
+  // transfer
+  int64_t n_tet = 0, nnz = 0;
+  const int64_t* rp = nullptr;
+  const int32_t* ci = nullptr;
+  const double* cv = nullptr;
+  // execution
+  bool use_graphs = true;
+  int poll = 8;
+  std::map<int, hipGraphExec_t> graphs;   // batch -> K-iteration graph
+  bool tuned = false;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<LaunchRec> recs;
+  double t_ms[KID_COUNT] = {};
+  int64_t t_n[KID_COUNT] = {};
+  double t_bytes[KID_COUNT] = {};
+
+  bool fp64() const { return prec == SPDE_FP64; }
+  size_t szm() const { return fp64() ? 8 : 4; }
+};
+
+}  // namespace spde
+
+namespace {
+
+// Chebyshev degree-2 smoother coefficients on [lmax/4, lmax] of D^-1 S~, with
+// lmax the Gershgorin bound (k2 + 12 a) / (k2 + 6 a) (capped at 2).
+void set_level(Level& L, int m, double kappa) {
+  const double H = 1.0 / m;
+  L.m = m;
+  L.nc = (int64_t)m * m * m;
+  L.k2 = kappa * kappa * H * H * H;
+  L.a = 1.5 * H;
+  const double lmax = std::min(2.0, (L.k2 + 12.0 * L.a) / (L.k2 + 6.0 * L.a));
+  const double lmin = lmax / 4.0;
+  const double th = 0.5 * (lmax + lmin), dl = 0.5 * (lmax - lmin);
+  const double sig = th / dl, rho0 = 1.0 / sig, rho1 = 1.0 / (2.0 * sig - rho0);
+  L.c0 = 1.0 / th;
+  L.c1 = 1.0 + rho1 * rho0;
+  L.c2 = 2.0 * rho1 / dl;
+  L.cA = L.c1 * L.c0 + L.c2 * (1.0 - L.c0);
+  L.cB = L.c2 * L.a * L.c0;
+}
+
+size_t coarse_bytes(const Ctx* c, int top) {
+  size_t tot = 0;
+  for (int l = top; l < c->nlev; ++l) tot += 4 * (size_t)c->lv[l].nc * c->szm();
+  return tot;
+}
+
+void plan_hierarchy(Ctx* c) {
+  c->nlev = 0;
+  for (int m = c->n; m >= 1; m >>= 1) set_level(c->lv[c->nlev++], m, c->kappa);
+  // persistent kernel: the largest levels (below the finest) that fit in LDS, at most 16^3
+  int top = c->nlev - 1;
+  for (int l = 1; l < c->nlev; ++l) {
+    if (c->lv[l].m <= 16 && coarse_bytes(c, l) <= (size_t)c->lds_limit) { top = l; break; }
+  }
+  c->top = top;
+  c->coarse_lds = coarse_bytes(c, top);
+  c->cp.nl = c->nlev - top;
+  int64_t off = 0;
+  for (int l = top; l < c->nlev; ++l) {
+    c->cp.lv[l - top] = c->lv[l];
+    c->cp.off[l - top] = off;
+    off += 4 * c->lv[l].nc;
+  }
+  for (int l = 0; l < c->nlev; ++l) {
+    c->shape_down[l] = 0;
+    c->shape_up[l] = c->fp64() ? 1 : 0;
+  }
+  int mx = 0;
+  for (int s = 0; s < kNumShapes; ++s) mx = std::max(mx, tiles_for(s, c->n));
+  c->nb_up0 = mx;   // capacity; the partial count used is tiles_for(shape_up[0], n)
+  c->nb_pb = operator_blocks(c->box);
+}
+
+size_t layout(Ctx* c, char* base) {
+  const int64_t nc = c->box.nc;
+  const size_t B = (size_t)c->max_batch;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  for (int p = 0; p < 2; ++p) c->F.vs[p] = (double*)take(B * 3 * nc * 8);
+  for (int p = 0; p < 2; ++p) c->F.vu[p] = (double*)take(B * nc * 8);
+  for (int p = 0; p < 2; ++p) c->F.z[p] = (void*)take(B * nc * c->szm());
+  for (int p = 0; p < 2; ++p) c->F.w[p] = (double*)take(B * nc * 8);
+  c->F.x = (double*)take(B * nc * 8);
+  for (int l = 1; l <= c->top && l < c->nlev; ++l) {
+    c->mgb[l] = take(B * c->lv[l].nc * c->szm());
+    c->mge[l] = take(B * c->lv[l].nc * c->szm());
+  }
+  c->F.part_up = (double*)take(B * (size_t)c->nb_up0 * 2 * 8);
+  c->F.part_pb = (double*)take(B * (size_t)c->nb_pb * 2 * 8);
+  c->F.sc = (Scalars*)take(B * sizeof(Scalars));
+  c->resid_out = (double*)take(B * 8);
+  return off;
+}
+
+// ---- timing -----------------------------------------------------------------
+
+hipEvent_t next_event(Ctx* c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+struct Timed {
+  Ctx* c;
+  int kid, iter, level;
+  hipStream_t st;
+  hipEvent_t e0 = nullptr;
+  Timed(Ctx* c_, int kid_, int iter_, hipStream_t st_, int level_ = 0)
+      : c(c_), kid(kid_), iter(iter_), level(level_), st(st_) {
+    if (c->timing) {
+      e0 = next_event(c);
+      if (e0) hipEventRecord(e0, st);
+    }
+  }
+  ~Timed() {
+    if (c->timing && e0) {
+      hipEvent_t e1 = next_event(c);
+      if (e1) {
+        hipEventRecord(e1, st);
+        c->recs.push_back({kid, iter, level, e0, e1});
+      }
+    }
+  }
+};
+
+// Algorithmic bytes of one launch for one slot (compulsory HBM traffic of the
+// method's data: every input read once, every output written once).
+double slot_bytes(const Ctx* c, int kid, int level, int iter, int wmode_active) {
+  const double nc = (double)c->box.nc, sz = (double)c->szm();
+  switch (kid) {
+    case KID_OPERATOR: {
+      double b = 0;
+      if (wmode_active & 1) b += nc * ((iter > 1 ? 64.0 : 32.0) + sz + 32.0);   // v update
+      if (wmode_active & 2) b += nc * (sz + 16.0 + (iter >= 3 ? 8.0 : 0.0) + (iter >= 4 ? 16.0 : 0.0));
+      return b;
+    }
+    case KID_MG_UP_FINE: return nc * (8.0 + sz / 8.0 + 24.0 + sz);
+    case KID_MG_DOWN_FINE: return nc * (8.0 + sz / 8.0);
+    case KID_MG_DOWN: { const double m = (double)c->lv[level].nc; return m * (sz + sz / 8.0); }
+    case KID_MG_UP: { const double m = (double)c->lv[level].nc; return m * (sz + sz / 8.0 + sz); }
+    case KID_MG_COARSE: return 2.0 * (double)c->lv[c->top].nc * sz;
+    default: return 0.0;
+  }
+}
+
+// ---- one MINRES iteration (all kernels), enqueued on st ------------------------
+
+spde_status enqueue_vcycle(Ctx* c, int batch, hipStream_t st, int iter, const void* b0, const void* b1,
+                           void* o0, void* o1, const Scalars* sc, double* part) {
+  const bool f64 = c->fp64();
+  {
+    Timed t(c, KID_MG_DOWN_FINE, iter, st);
+    HIPCHK(launch_mg_down(f64, c->shape_down[0], true, b0, b1, c->mgb[1], c->lv[0], batch, sc, st));
+  }
+  for (int l = 1; l < c->top; ++l) {
+    Timed t(c, KID_MG_DOWN, iter, st, l);
+    HIPCHK(launch_mg_down(f64, c->shape_down[l], false, c->mgb[l], c->mgb[l], c->mgb[l + 1], c->lv[l], batch, sc, st));
+  }
+  {
+    Timed t(c, KID_MG_COARSE, iter, st);
+    HIPCHK(launch_mg_coarse(f64, c->mgb[c->top], c->mge[c->top], c->cp, c->coarse_lds, batch, sc, st));
+  }
+  for (int l = c->top - 1; l >= 1; --l) {
+    Timed t(c, KID_MG_UP, iter, st, l);
+    HIPCHK(launch_mg_up(f64, c->shape_up[l], false, c->mgb[l], c->mgb[l], c->mge[l + 1], c->mge[l], c->mge[l],
+                        c->lv[l], batch, sc, nullptr, nullptr, nullptr, c->box, st));
+  }
+  {
+    Timed t(c, KID_MG_UP_FINE, iter, st);
+    HIPCHK(launch_mg_up(f64, c->shape_up[0], true, b0, b1, c->mge[1], o0, o1, c->lv[0], batch, sc,
+                        c->F.vs[0], c->F.vs[1], part, c->box, st));
+  }
+  return SPDE_OK;
+}
+
+spde_status enqueue_iteration(Ctx* c, int batch, hipStream_t st, int iter) {
+  spde_status s = enqueue_vcycle(c, batch, st, iter, c->F.vu[0], c->F.vu[1], c->F.z[0], c->F.z[1], c->F.sc,
+                                 c->F.part_up);
+  if (s != SPDE_OK) return s;
+  {
+    Timed t(c, KID_SCALAR, iter, st);
+    HIPCHK(launch_scalar(c->F, tiles_for(c->shape_up[0], c->n), c->nb_pb, batch, st));
+  }
+  {
+    Timed t(c, KID_OPERATOR, iter, st);
+    HIPCHK(launch_operator(c->fp64(), c->F, c->box, batch, st));
+  }
+  return SPDE_OK;
+}
+
+spde_status get_graph(Ctx* c, int batch, hipStream_t st, hipGraphExec_t* out) {
+  auto it = c->graphs.find(batch);
+  if (it != c->graphs.end()) { *out = it->second; return SPDE_OK; }
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  spde_status s = SPDE_OK;
+  for (int k = 0; k < c->poll && s == SPDE_OK; ++k) s = enqueue_iteration(c, batch, st, 0);
+  hipError_t e = hipStreamEndCapture(st, &g);
+  if (s != SPDE_OK) { if (g) hipGraphDestroy(g); return s; }
+  if (e != hipSuccess) return fail(SPDE_EHIP, "graph capture: %s", hipGetErrorString(e));
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(SPDE_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+  c->graphs[batch] = ex;
+  *out = ex;
+  return SPDE_OK;
+}
+
+void drop_graphs(Ctx* c) {
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
+spde_status check_ready(Ctx* c) {
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (!c->configured) return fail(SPDE_EINVAL, "spde_configure has not been called");
+  if (!c->ws) return fail(SPDE_EINVAL, "no workspace bound (spde_bind_workspace)");
+  return SPDE_OK;
+}
+
+hipStream_t pick_stream(Ctx* c, void* stream) {
+  return stream ? (hipStream_t)stream : c->own_stream;
+}
+
+// Close the timing records of a sample: per-launch bytes from the final
+// per-slot iteration counts, elapsed times from the event pairs.
+void close_timing(Ctx* c, int batch) {
+  if (!c->timing) return;
+  std::vector<int> iters(batch);
+  std::vector<int> states(batch);
+  for (int s = 0; s < batch; ++s) { iters[s] = c->host_sc[s].iters; states[s] = c->host_sc[s].state; }
+  for (const LaunchRec& r : c->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) continue;
+    double bytes = 0.0;
+    for (int s = 0; s < batch; ++s) {
+      const bool done = states[s] == ST_DONE || states[s] == ST_FINISH;
+      const int J = done ? iters[s] : (1 << 30);
+      if (r.kid == KID_OPERATOR) {
+        int mode = 0;
+        if (r.iter <= J) mode |= 1;
+        if (r.iter >= 2 && r.iter <= J + 1) mode |= 2;
+        bytes += slot_bytes(c, r.kid, 0, r.iter, mode);
+      } else if (r.iter >= 1 && r.iter <= J + 1) {
+        bytes += slot_bytes(c, r.kid, r.level, r.iter, 0);
+      }
+    }
+    c->t_ms[r.kid] += ms;
+    c->t_n[r.kid] += 1;
+    c->t_bytes[r.kid] += bytes;
+  }
+  c->recs.clear();
+  c->ev_used = 0;
+}
+
+}  // namespace
+
+// =============================================================================
+// C interface
+
+extern "C" {
+
+spde_status spde_setup_box(int n, double kappa, double g, spde_handle* out) {
+  if (!out) return fail(SPDE_EINVAL, "out is null");
+  *out = nullptr;
+  if (n < 4 || n > 1024 || (n & (n - 1))) return fail(SPDE_EINVAL, "n must be a power of two in [4, 1024], got %d", n);
+  if (!(kappa > 0.0) || !std::isfinite(kappa)) return fail(SPDE_EINVAL, "kappa must be positive and finite");
+  if (!(g > 0.0) || !std::isfinite(g)) return fail(SPDE_EINVAL, "g must be positive and finite");
+  Ctx* c = new Ctx();
+  c->n = n;
+  c->kappa = kappa;
+  c->g = g;
+  Box& b = c->box;
+  b.n = n;
+  b.n2 = (int64_t)n * n;
+  b.nc = b.n2 * n;
+  b.h = 1.0 / n;
+  b.h2 = b.h * b.h;
+  b.h3 = b.h2 * b.h;
+  b.kappa = kappa;
+  b.g = g;
+  b.q = 1.5 / b.h3;
+  b.k2h3 = kappa * kappa * b.h3;
+  b.h2q = b.h2 * b.q;
+  *out = reinterpret_cast<spde_handle>(c);
+  return SPDE_OK;
+}
+
+spde_status spde_configure(spde_handle h, spde_precision prec, double rtol, int max_iter, int max_batch) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (prec != SPDE_FP64 && prec != SPDE_MIXED) return fail(SPDE_EINVAL, "unknown precision %d", (int)prec);
+  if (!(rtol > 0.0 && rtol < 1.0)) return fail(SPDE_EINVAL, "rtol must lie in (0, 1)");
+  if (max_iter < 1 || max_iter > 100000) return fail(SPDE_EINVAL, "max_iter must lie in [1, 100000]");
+  if (max_batch < 1 || max_batch > 4096) return fail(SPDE_EINVAL, "max_batch must lie in [1, 4096]");
+  drop_graphs(c);
+  c->prec = prec;
+  c->rtol = rtol;
+  c->max_iter = max_iter;
+  c->max_batch = max_batch;
+  c->configured = true;
+  c->ws = nullptr;
+  c->ws_bytes = 0;
+  c->tuned = false;
+  plan_hierarchy(c);
+  return SPDE_OK;
+}
+
+size_t spde_workspace_bytes(spde_handle h) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c || !c->configured) return 0;
+  return layout(c, nullptr);
+}
+
+spde_status spde_bind_workspace(spde_handle h, void* dev_ptr, size_t bytes) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (!c->configured) return fail(SPDE_EINVAL, "spde_configure has not been called");
+  if (!dev_ptr) return fail(SPDE_EINVAL, "workspace pointer is null");
+  if ((uintptr_t)dev_ptr & 255) return fail(SPDE_EINVAL, "workspace must be 256-byte aligned");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (c->device != dev) {
+    if (c->own_stream) { hipStreamDestroy(c->own_stream); c->own_stream = nullptr; }
+    c->device = dev;
+    int lds = 65536;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+      c->lds_limit = lds;
+    HIPCHK(hipStreamCreate(&c->own_stream));
+    if (!c->host_sc) HIPCHK(hipHostMalloc((void**)&c->host_sc, 4096 * sizeof(Scalars), hipHostMallocDefault));
+    if (!c->host_res) HIPCHK(hipHostMalloc((void**)&c->host_res, 4096 * sizeof(double), hipHostMallocDefault));
+  }
+  drop_graphs(c);
+  plan_hierarchy(c);
+  const size_t need = layout(c, nullptr);
+  if (bytes < need) return fail(SPDE_ENOMEM, "workspace has %zu bytes, %zu needed", bytes, need);
+  layout(c, (char*)dev_ptr);
+  c->ws = (char*)dev_ptr;
+  c->ws_bytes = bytes;
+  HIPCHK(prepare_coarse(c->fp64(), c->coarse_lds));
+  return SPDE_OK;
+}
+
+spde_status spde_build_transfer(spde_handle h, int64_t n_vert, const double* xyz_host, int64_t n_tet,
+                                const int32_t* tet_host, int64_t** row_ptr_host, int32_t** col_host,
+                                double** val_host, int64_t* nnz) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (!xyz_host || !tet_host || !row_ptr_host || !col_host || !val_host || !nnz)
+    return fail(SPDE_EINVAL, "null argument");
+  if (n_vert < 4 || n_tet < 1) return fail(SPDE_EINVAL, "empty mesh");
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<double> cv;
+  char err[256] = {0};
+  if (build_transfer_csr(c->n, n_vert, xyz_host, n_tet, tet_host, rp, ci, cv, err, sizeof err) != 0)
+    return fail(SPDE_EINVAL, "%s", err);
+  *row_ptr_host = (int64_t*)malloc(rp.size() * sizeof(int64_t));
+  *col_host = (int32_t*)malloc(std::max<size_t>(1, ci.size()) * sizeof(int32_t));
+  *val_host = (double*)malloc(std::max<size_t>(1, cv.size()) * sizeof(double));
+  if (!*row_ptr_host || !*col_host || !*val_host) return fail(SPDE_ENOMEM, "host allocation failed");
+  memcpy(*row_ptr_host, rp.data(), rp.size() * sizeof(int64_t));
+  memcpy(*col_host, ci.data(), ci.size() * sizeof(int32_t));
+  memcpy(*val_host, cv.data(), cv.size() * sizeof(double));
+  *nnz = (int64_t)ci.size();
+  return SPDE_OK;
+}
+
+spde_status spde_set_transfer(spde_handle h, int64_t n_tet, int64_t nnz, const int64_t* row_ptr_dev,
+                              const int32_t* col_dev, const double* val_dev) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (n_tet < 1 || nnz < 0 || !row_ptr_dev || (nnz > 0 && (!col_dev || !val_dev)))
+    return fail(SPDE_EINVAL, "invalid transfer matrix");
+  c->n_tet = n_tet;
+  c->nnz = nnz;
+  c->rp = row_ptr_dev;
+  c->ci = col_dev;
+  c->cv = val_dev;
+  return SPDE_OK;
+}
+
+spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* u_tet_dev, double* u_box_dev,
+                        double* sigma_dev, void* stream, int* iters_host, double* relres_host) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  spde_status s = check_ready(c);
+  if (s != SPDE_OK) return s;
+  if (batch < 1) return fail(SPDE_EINVAL, "batch must be >= 1");
+  if (batch > c->max_batch) return fail(SPDE_ENOMEM, "batch %d exceeds max_batch %d", batch, c->max_batch);
+  if (!xi_dev) return fail(SPDE_EINVAL, "xi is null");
+  if (u_tet_dev && !c->rp) return fail(SPDE_EINVAL, "u_tet requested but no transfer set");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = pick_stream(c, stream);
+  const Box& bx = c->box;
+  const double scale = -c->g * std::pow(bx.h, 1.5);
+  {
+    Timed t(c, KID_INIT, 0, st);
+    HIPCHK(launch_init(c->F, bx, xi_dev, scale, batch, c->rtol, c->max_iter, st));
+  }
+  const bool graphs = c->use_graphs && !c->timing && st != nullptr;
+  int launched = 0;
+  const int cap = c->max_iter + 2;
+  bool all_done = false;
+  while (!all_done && launched < cap + c->poll) {
+    hipGraphExec_t ex = nullptr;
+    if (graphs && get_graph(c, batch, st, &ex) != SPDE_OK) {
+      // capture not available on this stream: fall back to plain launches
+      hipGetLastError();
+      c->use_graphs = false;
+      ex = nullptr;
+    }
+    if (ex) {
+      HIPCHK(hipGraphLaunch(ex, st));
+    } else {
+      for (int k = 0; k < c->poll; ++k) {
+        s = enqueue_iteration(c, batch, st, launched + k + 1);
+        if (s != SPDE_OK) return s;
+      }
+    }
+    launched += c->poll;
+    HIPCHK(hipMemcpyAsync(c->host_sc, c->F.sc, batch * sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    all_done = true;
+    for (int b = 0; b < batch; ++b) {
+      const int stt = c->host_sc[b].state;
+      if (stt == ST_ACTIVE) { all_done = false; break; }
+    }
+  }
+  bool notconv = false, failed = false;
+  for (int b = 0; b < batch; ++b) {
+    const Scalars& sc = c->host_sc[b];
+    if (sc.state == ST_FAILED) failed = true;
+    if (sc.state == ST_ACTIVE || (sc.flags & FL_NOTCONV)) notconv = true;
+    if (iters_host) iters_host[b] = sc.state == ST_ACTIVE ? launched : sc.iters;
+  }
+  HIPCHK(launch_fix_solution(c->F, bx, batch, st));
+  if (u_box_dev) HIPCHK(hipMemcpyAsync(u_box_dev, c->F.x, (size_t)batch * bx.nc * 8, hipMemcpyDeviceToDevice, st));
+  if (sigma_dev || relres_host) {
+    double* sig_int = relres_host ? c->F.vs[0] : nullptr;
+    {
+      Timed t(c, KID_FLUX, 0, st);
+      HIPCHK(launch_flux(c->F.x, sig_int, sigma_dev, bx, batch, st));
+    }
+    if (relres_host) {
+      {
+        Timed t(c, KID_RESID, 0, st);
+        HIPCHK(launch_resid(sig_int, c->F.x, xi_dev, scale, bx, batch, c->F.part_pb, c->resid_out, st));
+      }
+      HIPCHK(hipMemcpyAsync(c->host_res, c->resid_out, batch * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+  }
+  if (u_tet_dev) {
+    Timed t(c, KID_SPMM, 0, st);
+    HIPCHK(launch_spmm(c->rp, c->ci, c->cv, c->F.x, u_tet_dev, c->n_tet, c->nnz, bx.nc, batch, st));
+  }
+  if (relres_host || c->timing) {
+    HIPCHK(hipStreamSynchronize(st));
+    if (relres_host) for (int b = 0; b < batch; ++b) relres_host[b] = c->host_res[b];
+  }
+  close_timing(c, batch);
+  if (failed) return fail(SPDE_EFAILED, "breakdown or non-finite value in some sample");
+  if (notconv) return fail(SPDE_ENOTCONV, "max_iter reached for some sample");
+  return SPDE_OK;
+}
+
+spde_status spde_restrict_noise(int n_fine, int batch, const double* xi_f_dev, double* xi_c_dev, void* stream) {
+  if (n_fine < 2 || (n_fine & 1)) return fail(SPDE_EINVAL, "n_fine must be even and >= 2");
+  if (batch < 1) return fail(SPDE_EINVAL, "batch must be >= 1");
+  if (!xi_f_dev || !xi_c_dev) return fail(SPDE_EINVAL, "null pointer");
+  HIPCHK(launch_restrict_noise(xi_f_dev, xi_c_dev, n_fine, batch, (hipStream_t)stream));
+  return SPDE_OK;
+}
+
+spde_status spde_apply_operator(spde_handle h, int batch, const double* x_sigma_dev, const double* x_u_dev,
+                                double* y_sigma_dev, double* y_u_dev, void* stream) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  spde_status s = check_ready(c);
+  if (s != SPDE_OK) return s;
+  if (batch < 1 || batch > c->max_batch) return fail(SPDE_EINVAL, "batch out of range");
+  if (!x_sigma_dev || !x_u_dev || !y_sigma_dev || !y_u_dev) return fail(SPDE_EINVAL, "null pointer");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = pick_stream(c, stream);
+  Fields G = c->F;
+  G.z[0] = G.w[0];            // a float64 cell buffer for zhat = x_u
+  HIPCHK(launch_ext_to_int(x_sigma_dev, x_u_dev, G, c->box, batch, st));
+  HIPCHK(launch_probe_scalars(G.sc, batch, st));
+  HIPCHK(launch_operator(true, G, c->box, batch, st));
+  HIPCHK(launch_int_to_ext(G, y_sigma_dev, y_u_dev, c->box, batch, st));
+  return SPDE_OK;
+}
+
+spde_status spde_apply_vcycle(spde_handle h, int batch, const double* r_dev, double* z_dev, void* stream) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  spde_status s = check_ready(c);
+  if (s != SPDE_OK) return s;
+  if (batch < 1 || batch > c->max_batch) return fail(SPDE_EINVAL, "batch out of range");
+  if (!r_dev || !z_dev) return fail(SPDE_EINVAL, "null pointer");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = pick_stream(c, stream);
+  void* out = c->fp64() ? (void*)z_dev : c->F.z[0];
+  s = enqueue_vcycle(c, batch, st, 0, r_dev, r_dev, out, out, nullptr, nullptr);
+  if (s != SPDE_OK) return s;
+  if (!c->fp64()) HIPCHK(launch_f32_to_f64((const float*)c->F.z[0], z_dev, (int64_t)batch * c->box.nc, st));
+  return SPDE_OK;
+}
+
+spde_status spde_apply_transfer(spde_handle h, int batch, const double* u_box_dev, double* u_tet_dev, void* stream) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (!c->rp) return fail(SPDE_EINVAL, "no transfer set");
+  if (batch < 1 || !u_box_dev || !u_tet_dev) return fail(SPDE_EINVAL, "invalid argument");
+  if (c->device >= 0) HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_spmm(c->rp, c->ci, c->cv, u_box_dev, u_tet_dev, c->n_tet, c->nnz, c->box.nc, batch,
+                     (hipStream_t)stream));
+  return SPDE_OK;
+}
+
+spde_status spde_set_graphs(spde_handle h, int enable) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  c->use_graphs = enable != 0;
+  return SPDE_OK;
+}
+
+spde_status spde_set_poll_interval(spde_handle h, int iters) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (iters < 1 || iters > 256) return fail(SPDE_EINVAL, "poll interval must lie in [1, 256]");
+  if (iters != c->poll) drop_graphs(c);
+  c->poll = iters;
+  return SPDE_OK;
+}
+
+spde_status spde_timing(spde_handle h, int enable) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (enable < 0) {
+    for (int k = 0; k < KID_COUNT; ++k) { c->t_ms[k] = 0; c->t_n[k] = 0; c->t_bytes[k] = 0; }
+    c->timing = false;
+    return SPDE_OK;
+  }
+  c->timing = enable != 0;
+  return SPDE_OK;
+}
+
+int spde_kernel_count(void) { return KID_COUNT; }
+
+const char* spde_kernel_name(int id) { return (id >= 0 && id < KID_COUNT) ? kKernelNames[id] : nullptr; }
+
+spde_status spde_timing_get(spde_handle h, int id, double* total_ms, int64_t* launches, double* bytes_per_launch) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (id < 0 || id >= KID_COUNT) return fail(SPDE_EINVAL, "kernel id out of range");
+  if (total_ms) *total_ms = c->t_ms[id];
+  if (launches) *launches = c->t_n[id];
+  if (bytes_per_launch) *bytes_per_launch = c->t_n[id] ? c->t_bytes[id] / (double)c->t_n[id] : 0.0;
+  return SPDE_OK;
+}
+
+spde_status spde_info(spde_handle h, int* levels, int* persistent_top_n, int* device_lds_bytes) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c || !c->configured) return fail(SPDE_EINVAL, "handle not configured");
+  if (levels) *levels = c->nlev;
+  if (persistent_top_n) *persistent_top_n = c->lv[c->top].m;
+  if (device_lds_bytes) *device_lds_bytes = c->lds_limit;
+  return SPDE_OK;
+}
+
+void spde_free_host(void* p) { free(p); }
+
+void spde_destroy(spde_handle h) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return;
+  drop_graphs(c);
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+  if (c->own_stream) hipStreamDestroy(c->own_stream);
+  if (c->host_sc) hipHostFree(c->host_sc);
+  if (c->host_res) hipHostFree(c->host_res);
+  delete c;
+}
+
+const char* spde_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

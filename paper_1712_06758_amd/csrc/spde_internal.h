@@ -1,0 +1,149 @@
+// Internal types shared by the HIP kernels and the host orchestration.
+//
+// Storage (all device, inside the caller's workspace), batch-outermost:
+//   a cell array of one sample is n^3 values in cell order c = i + n (j + n k);
+//   a face field of one sample is 3 such arrays, entry c of array d holding
+//   the face on the low side of cell c in direction d (the face at i_d = 0 is
+//   on the box boundary and always 0; the high boundary face of the last cell
+//   is not stored).  All face arrays therefore share the cell indexing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace spde {
+
+constexpr int kMaxLevels = 12;
+constexpr int kBlock = 256;          // threads per block of the streaming kernels
+
+// Per-sample solver state (one per batch slot).
+enum SlotState : int {
+  ST_ACTIVE = 0,   // iterating
+  ST_FINISH = 1,   // converged or capped: the operator pass applies the last x update
+  ST_DONE   = 2,   // solution final in x
+  ST_FAILED = 3,   // breakdown / non-finite
+  ST_IDLE   = 4    // slot not in use
+};
+
+enum SlotFlags : int {
+  FL_ZERO    = 1,  // right-hand side was exactly zero: solution is 0
+  FL_NOTCONV = 2   // stopped at max_iter
+};
+
+// MINRES scalars of one sample.  Notation: iteration j works on the Lanczos
+// vector v_j and its preconditioned image zhat_j = P^-1 v_j (not yet
+// normalised); gamma_j^2 = <zhat_j, v_j>, delta_j = <A z_j, z_j> with
+// z_j = zhat_j / gamma_j.
+struct alignas(16) Scalars {
+  double gamma, gamma_prev;   // gamma_j, gamma_{j-1}
+  double delta;               // delta_j
+  double c, s, c_prev, s_prev;
+  double eta, eta0;
+  // coefficients consumed by the operator pass of iteration `pit`
+  double zs;                  // 1 / gamma_j
+  double a_v;                 // delta_j / gamma_j
+  double b_v;                 // gamma_j / gamma_{j-1}
+  double wz, ww_prev, ww;     // w_j = wz zhat_{j-1} + ww_prev w_{j-2} + ww w_{j-1}
+  double xw;                  // x_{j-1} = x_{j-2} + xw w_j
+  double tol;                 // relative stopping tolerance on |eta| / eta0
+  int it;                     // iteration the V-cycle and the scalar step work on
+  int pit;                    // iteration the operator pass works on
+  int state;
+  int flags;
+  int wmode;                  // -1 no w/x update, 0 first (no reads), 1 no w_{j-2}, 2 full
+  int iters;                  // iterations when finished
+  int max_iter;
+  int pad;
+};
+
+// Box constants.
+struct Box {
+  int n;
+  int64_t n2;
+  int64_t nc;        // n^3
+  double h, h2, h3;
+  double kappa, g;
+  double q;          // 3 / (2 h^3): inverse of the face diagonal of M
+  double k2h3;       // kappa^2 h^3
+  double h2q;        // h^2 q
+};
+
+// One multigrid level: operator S~ = k2 I + a L (L the Neumann graph
+// Laplacian), Chebyshev smoother coefficients of the degree-2 polynomial.
+struct Level {
+  int m;             // cells per edge
+  int64_t nc;        // m^3
+  double k2;         // kappa^2 H^3
+  double a;          // 3 H / 2
+  double c0, c1, c2; // y = c0 D^-1 r ; x = c1 y + c2 D^-1 (r - A y)
+  double cA, cB;     // pre-smoothing from zero in terms of bhat = D^-1 b:
+                     // x = cA bhat + (cB / d) * sum_nbr bhat
+};
+
+struct CoarseParams {
+  int nl;                      // levels handled (top first, last is 1^3 or the coarsest)
+  Level lv[kMaxLevels];
+  int64_t off[kMaxLevels];     // element offset of each level's 4 arrays in LDS
+};
+
+// Device pointers of the MINRES state.  Index [p] is the buffer parity.
+struct Fields {
+  double* vs[2];     // face Lanczos vectors: vs[p] + (slot*3 + d) * nc
+  double* vu[2];     // cell Lanczos vectors
+  void*   z[2];      // preconditioned cell vectors (float or double)
+  double* w[2];      // MINRES direction vectors (cell part)
+  double* x;         // solution (cell part)
+  double* part_up;   // [slot][nb_up][2] partial sums of <zhat, v_u>, zhat^T A zhat
+  double* part_pb;   // [slot][nb_pb]    partial sums of q |v_sigma|^2
+  Scalars* sc;       // [slot]
+};
+
+// Per-sample offsets.
+__host__ __device__ inline int64_t cell_off(int slot, int64_t nc) { return (int64_t)slot * nc; }
+__host__ __device__ inline int64_t face_off(int slot, int d, int64_t nc) { return ((int64_t)slot * 3 + d) * nc; }
+
+// Kernel classes (for timing and names).
+enum KernelId : int {
+  KID_INIT = 0, KID_MG_DOWN_FINE, KID_MG_DOWN, KID_MG_COARSE, KID_MG_UP, KID_MG_UP_FINE,
+  KID_SCALAR, KID_OPERATOR, KID_OUTPUT, KID_FLUX, KID_RESID, KID_SPMM, KID_RESTRICT,
+  KID_COUNT
+};
+
+}  // namespace spde
+
+// ---------------------------------------------------------------------------
+// host launchers (defined in spde_kernels.hip)
+namespace spde {
+constexpr int kNumShapes = 6;
+extern const int kShapes[kNumShapes][3];
+bool shape_ok_up(int shape, bool fp64);
+bool shape_ok_down(int shape, bool fp64);
+int tiles_for(int shape, int m);
+int operator_blocks(const Box& bx);
+
+hipError_t launch_init(const Fields& F, const Box& bx, const double* xi, double scale, int batch, double tol,
+                       int max_iter, hipStream_t st);
+hipError_t launch_mg_down(bool fp64, int shape, bool fine, const void* b0, const void* b1, void* rH,
+                          const Level& L, int batch, const Scalars* sc, hipStream_t st);
+hipError_t launch_mg_up(bool fp64, int shape, bool fine, const void* b0, const void* b1, const void* eH, void* o0,
+                        void* o1, const Level& L, int batch, const Scalars* sc, const double* vs0,
+                        const double* vs1, double* part, const Box& bx, hipStream_t st);
+hipError_t prepare_coarse(bool fp64, size_t lds_bytes);
+hipError_t launch_mg_coarse(bool fp64, const void* btop, void* etop, const CoarseParams& P, size_t lds_bytes,
+                            int batch, const Scalars* sc, hipStream_t st);
+hipError_t launch_scalar(const Fields& F, int nb_up, int nb_pb, int batch, hipStream_t st);
+hipError_t launch_operator(bool z_fp64, const Fields& F, const Box& bx, int batch, hipStream_t st);
+hipError_t launch_fix_solution(const Fields& F, const Box& bx, int batch, hipStream_t st);
+hipError_t launch_flux(const double* u, double* sig_int, double* sig_ext, const Box& bx, int batch,
+                       hipStream_t st);
+hipError_t launch_resid(const double* sig, const double* u, const double* xi, double scale, const Box& bx,
+                        int batch, double* part, double* out, hipStream_t st);
+hipError_t launch_spmm(const int64_t* rp, const int32_t* ci, const double* cv, const double* u, double* out,
+                       int64_t ntet, int64_t nnz, int64_t nc, int batch, hipStream_t st);
+hipError_t launch_restrict_noise(const double* xf, double* xc, int nf, int batch, hipStream_t st);
+hipError_t launch_ext_to_int(const double* xs, const double* xu, const Fields& F, const Box& bx, int batch,
+                             hipStream_t st);
+hipError_t launch_int_to_ext(const Fields& F, double* ys, double* yu, const Box& bx, int batch, hipStream_t st);
+hipError_t launch_probe_scalars(Scalars* sc, int batch, hipStream_t st);
+hipError_t launch_f32_to_f64(const float* s, double* d, int64_t count, hipStream_t st);
+}  // namespace spde

@@ -1,0 +1,801 @@
+// HIP kernels (gfx950) of the SPDE field sampler.
+//
+// The solve is MINRES on the RT0/P0 saddle-point system of eq. linsys,
+// preconditioned by blkdiag(diag(M), V) where V is one V-cycle of geometric
+// multigrid on S~ = kappa^2 W + B diag(M)^-1 B^T (eq. ldu's approximate Schur
+// complement with the kappa^2 W block).  Only the cell part of the MINRES
+// iterate is stored ("u-only" MINRES): the face parts of x and w never feed
+// back into the recurrence, and the face part of z = P^-1 v is diag(M)^-1 v,
+// applied on the fly.
+//
+// Per iteration j (all launches cover every slot of the batch; each block
+// reads its slot's state and exits unless the slot is iterating):
+//   mg_down (fine, then per level)  : smooth from zero, restrict the residual
+//   mg_coarse                        : the levels that fit in LDS, one block per slot
+//   mg_up (per level, then fine)     : prolong, correct, smooth; the fine launch
+//                                      writes zhat_j and the partial sums of
+//                                      <zhat_j, v_j> and zhat_j^T A zhat_j
+//   scalar                           : per-slot reductions, Givens rotation,
+//                                      convergence test
+//   operator                         : v_{j+1} = A z_j - (delta/gamma) v_j - (gamma/gamma_prev) v_{j-1}
+//                                      and the delayed w/x update of step j-1
+#include "spde_internal.h"
+
+namespace spde {
+
+// ---------------------------------------------------------------------------
+// helpers
+
+// Blocks are dispatched round-robin over the 8 XCDs of the MI355X; give each
+// XCD a contiguous range of logical blocks so that stencil neighbours share
+// that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  if (nblocks & 7) return bid;
+  const int per = nblocks >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
+
+// Sum over the block; the result is valid in thread 0.  Fixed order.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ int nnbr(int x, int y, int z, int m) {
+  return (x > 0) + (x < m - 1) + (y > 0) + (y < m - 1) + (z > 0) + (z < m - 1);
+}
+
+// ---------------------------------------------------------------------------
+// initialisation: v_1 = F = [0; scale * xi], state reset
+
+__global__ __launch_bounds__(kBlock) void k_init(Fields F, Box bx, const double* __restrict__ xi,
+                                                 double scale, int nb, double tol, int max_iter) {
+  const int slot = blockIdx.x / nb;
+  const int blk = blockIdx.x - slot * nb;
+  const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
+  if (c < bx.nc) {
+    F.vu[1][cell_off(slot, bx.nc) + c] = scale * xi[cell_off(slot, bx.nc) + c];
+    F.vs[1][face_off(slot, 0, bx.nc) + c] = 0.0;
+    F.vs[1][face_off(slot, 1, bx.nc) + c] = 0.0;
+    F.vs[1][face_off(slot, 2, bx.nc) + c] = 0.0;
+  }
+  if (blk == 0 && threadIdx.x == 0) {
+    Scalars s{};
+    s.it = 1; s.pit = 0; s.state = ST_ACTIVE; s.flags = 0; s.wmode = -1;
+    s.c = s.c_prev = 1.0; s.s = s.s_prev = 0.0;
+    s.gamma_prev = 1.0; s.tol = tol; s.max_iter = max_iter; s.iters = 0;
+    F.sc[slot] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// multigrid: smooth from zero + residual + restriction (one level, 3-D tile)
+//
+// With bhat = D^-1 b the degree-2 Chebyshev smoother from a zero guess is
+//   x = cA bhat + (cB / d) sum_nbr bhat,
+// and the restricted residual is r_H[I] = sum over the 8 children of
+//   d (bhat - x) + a sum_nbr x.
+
+template <typename TM, typename TB, int TX, int TY, int TZ, bool FINE>
+__global__ __launch_bounds__(kBlock) void k_mg_down(const TB* __restrict__ b0, const TB* __restrict__ b1,
+                                                    TM* __restrict__ rH, Level L, int nb,
+                                                    const Scalars* __restrict__ sc) {
+  constexpr int BX = TX + 4, BY = TY + 4, BZ = TZ + 4;
+  constexpr int XX = TX + 2, XY = TY + 2, XZ = TZ + 2;
+  __shared__ TM sb[BX * BY * BZ];
+  __shared__ TM sx[XX * XY * XZ];
+  const int m = L.m;
+  const int tpx = (m + TX - 1) / TX, tpy = (m + TY - 1) / TY;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int slot = lb / nb, t = lb - slot * nb;
+  const TB* b = b0;
+  if (sc) {
+    if (sc[slot].state != ST_ACTIVE) return;
+    if (FINE && (sc[slot].it & 1)) b = b1;
+  }
+  b += (int64_t)slot * L.nc;
+  const int x0 = (t % tpx) * TX, y0 = ((t / tpx) % tpy) * TY, z0 = (t / (tpx * tpy)) * TZ;
+  const TM k2 = (TM)L.k2, a = (TM)L.a, cA = (TM)L.cA, cB = (TM)L.cB;
+
+  for (int e = threadIdx.x; e < BX * BY * BZ; e += kBlock) {
+    const int lx = e % BX, ly = (e / BX) % BY, lz = e / (BX * BY);
+    const int gx = x0 + lx - 2, gy = y0 + ly - 2, gz = z0 + lz - 2;
+    TM v = 0;
+    if (gx >= 0 && gx < m && gy >= 0 && gy < m && gz >= 0 && gz < m) {
+      const TM d = k2 + a * (TM)nnbr(gx, gy, gz, m);
+      v = (TM)b[gx + (int64_t)m * (gy + (int64_t)m * gz)] / d;
+    }
+    sb[e] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < XX * XY * XZ; e += kBlock) {
+    const int lx = e % XX, ly = (e / XX) % XY, lz = e / (XX * XY);
+    const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
+    TM v = 0;
+    if (gx >= 0 && gx < m && gy >= 0 && gy < m && gz >= 0 && gz < m) {
+      const int s = (lx + 1) + BX * ((ly + 1) + BY * (lz + 1));
+      const TM sum = sb[s - 1] + sb[s + 1] + sb[s - BX] + sb[s + BX] + sb[s - BX * BY] + sb[s + BX * BY];
+      const TM d = k2 + a * (TM)nnbr(gx, gy, gz, m);
+      v = cA * sb[s] + (cB / d) * sum;
+    }
+    sx[e] = v;
+  }
+  __syncthreads();
+  constexpr int CX = TX / 2, CY = TY / 2, CZ = TZ / 2;
+  const int mH = m >> 1;
+  TM* r = rH + (int64_t)slot * mH * mH * mH;
+  for (int e = threadIdx.x; e < CX * CY * CZ; e += kBlock) {
+    const int cx = e % CX, cy = (e / CX) % CY, cz = e / (CX * CY);
+    const int gcx = (x0 >> 1) + cx, gcy = (y0 >> 1) + cy, gcz = (z0 >> 1) + cz;
+    if (gcx >= mH || gcy >= mH || gcz >= mH) continue;
+    TM acc = 0;
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) {
+      const int lx = 2 * cx + (ch & 1), ly = 2 * cy + ((ch >> 1) & 1), lz = 2 * cz + (ch >> 2);
+      const int s = (lx + 2) + BX * ((ly + 2) + BY * (lz + 2));
+      const int u = (lx + 1) + XX * ((ly + 1) + XY * (lz + 1));
+      const TM d = k2 + a * (TM)nnbr(x0 + lx, y0 + ly, z0 + lz, m);
+      const TM sum = sx[u - 1] + sx[u + 1] + sx[u - XX] + sx[u + XX] + sx[u - XX * XY] + sx[u + XX * XY];
+      acc += d * (sb[s] - sx[u]) + a * sum;
+    }
+    r[gcx + (int64_t)mH * (gcy + (int64_t)mH * gcz)] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// multigrid: prolongation + correction + post-smoothing (one level, 3-D tile)
+//
+// The pre-smoothed iterate is recomputed from b on the tile's halo (no stored
+// state), the coarse correction is piecewise-constant prolongation of e_H,
+// and the post-smoother applies the same Chebyshev polynomial to the residual:
+//   r = b - A x ; y = c0 D^-1 r ; out = x + c1 y + c2 D^-1 (r - A y).
+// The fine launch also accumulates, per block, the partial sums
+//   <zhat, v_u>  and  zhat^T A zhat  with zhat = (diag(M)^-1 v_sigma, zhat_u),
+// from which the scalar step forms gamma_j and delta_j.
+
+template <typename TM, typename TB, typename TO, int TX, int TY, int TZ, bool FINE>
+__global__ __launch_bounds__(kBlock) void k_mg_up(const TB* __restrict__ b0, const TB* __restrict__ b1,
+                                                  const TM* __restrict__ eH, TO* __restrict__ o0,
+                                                  TO* __restrict__ o1, Level L, int nb,
+                                                  const Scalars* __restrict__ sc,
+                                                  const double* __restrict__ vs0,
+                                                  const double* __restrict__ vs1,
+                                                  double* __restrict__ part, Box bxc) {
+  constexpr int BX = TX + 6, BY = TY + 6, BZ = TZ + 6;
+  constexpr int XX = TX + 4, XY = TY + 4, XZ = TZ + 4;
+  constexpr int YX = TX + 2, YY = TY + 2, YZ = TZ + 2;
+  __shared__ TM sb[BX * BY * BZ];
+  __shared__ TM sx[XX * XY * XZ];
+  __shared__ TM sy[YX * YY * YZ];
+  __shared__ double red[kBlock / 64];
+  const int m = L.m;
+  const int tpx = (m + TX - 1) / TX, tpy = (m + TY - 1) / TY;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int slot = lb / nb, t = lb - slot * nb;
+  const TB* b = b0;
+  TO* o = o0;
+  const double* vs = vs0;
+  if (sc) {
+    if (sc[slot].state != ST_ACTIVE) return;
+    if (FINE && (sc[slot].it & 1)) { b = b1; o = o1; vs = vs1; }
+  }
+  b += (int64_t)slot * L.nc;
+  o += (int64_t)slot * L.nc;
+  const int mH = m >> 1;
+  const TM* e = eH + (int64_t)slot * mH * mH * mH;
+  const int x0 = (t % tpx) * TX, y0 = ((t / tpx) % tpy) * TY, z0 = (t / (tpx * tpy)) * TZ;
+  const TM k2 = (TM)L.k2, a = (TM)L.a, cA = (TM)L.cA, cB = (TM)L.cB;
+  const TM c0 = (TM)L.c0, c1 = (TM)L.c1, c2 = (TM)L.c2;
+
+  for (int i = threadIdx.x; i < BX * BY * BZ; i += kBlock) {
+    const int lx = i % BX, ly = (i / BX) % BY, lz = i / (BX * BY);
+    const int gx = x0 + lx - 3, gy = y0 + ly - 3, gz = z0 + lz - 3;
+    TM v = 0;
+    if (gx >= 0 && gx < m && gy >= 0 && gy < m && gz >= 0 && gz < m) {
+      const TM d = k2 + a * (TM)nnbr(gx, gy, gz, m);
+      v = (TM)b[gx + (int64_t)m * (gy + (int64_t)m * gz)] / d;
+    }
+    sb[i] = v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < XX * XY * XZ; i += kBlock) {
+    const int lx = i % XX, ly = (i / XX) % XY, lz = i / (XX * XY);
+    const int gx = x0 + lx - 2, gy = y0 + ly - 2, gz = z0 + lz - 2;
+    TM v = 0;
+    if (gx >= 0 && gx < m && gy >= 0 && gy < m && gz >= 0 && gz < m) {
+      const int s = (lx + 1) + BX * ((ly + 1) + BY * (lz + 1));
+      const TM sum = sb[s - 1] + sb[s + 1] + sb[s - BX] + sb[s + BX] + sb[s - BX * BY] + sb[s + BX * BY];
+      const TM d = k2 + a * (TM)nnbr(gx, gy, gz, m);
+      v = cA * sb[s] + (cB / d) * sum + e[(gx >> 1) + (int64_t)mH * ((gy >> 1) + (int64_t)mH * (gz >> 1))];
+    }
+    sx[i] = v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < YX * YY * YZ; i += kBlock) {
+    const int lx = i % YX, ly = (i / YX) % YY, lz = i / (YX * YY);
+    const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
+    TM v = 0;
+    if (gx >= 0 && gx < m && gy >= 0 && gy < m && gz >= 0 && gz < m) {
+      const int s = (lx + 2) + BX * ((ly + 2) + BY * (lz + 2));
+      const int u = (lx + 1) + XX * ((ly + 1) + XY * (lz + 1));
+      const TM sum = sx[u - 1] + sx[u + 1] + sx[u - XX] + sx[u + XX] + sx[u - XX * XY] + sx[u + XX * XY];
+      const TM d = k2 + a * (TM)nnbr(gx, gy, gz, m);
+      const TM r = d * (sb[s] - sx[u]) + a * sum;
+      v = c0 * r / d;
+    }
+    sy[i] = v;
+  }
+  __syncthreads();
+  double p_zv = 0.0, p_azz = 0.0;
+  for (int i = threadIdx.x; i < TX * TY * TZ; i += kBlock) {
+    const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+    if (gx >= m || gy >= m || gz >= m) continue;
+    const int s = (lx + 3) + BX * ((ly + 3) + BY * (lz + 3));
+    const int u = (lx + 2) + XX * ((ly + 2) + XY * (lz + 2));
+    const int w = (lx + 1) + YX * ((ly + 1) + YY * (lz + 1));
+    const TM d = k2 + a * (TM)nnbr(gx, gy, gz, m);
+    const TM sxn = sx[u - 1] + sx[u + 1] + sx[u - XX] + sx[u + XX] + sx[u - XX * XY] + sx[u + XX * XY];
+    const TM syn = sy[w - 1] + sy[w + 1] + sy[w - YX] + sy[w + YX] + sy[w - YX * YY] + sy[w + YX * YY];
+    const TM r = d * (sb[s] - sx[u]) + a * sxn;
+    const TM t2 = r - (d * sy[w] - a * syn);
+    const TM out = sx[u] + c1 * sy[w] + (c2 / d) * t2;
+    const int64_t g = gx + (int64_t)m * (gy + (int64_t)m * gz);
+    const TO zo = (TO)out;
+    o[g] = zo;
+    if (FINE && part) {
+      const double z = (double)zo;
+      const int64_t nc = bxc.nc;
+      const double* vx = vs + face_off(slot, 0, nc);
+      const double* vy = vs + face_off(slot, 1, nc);
+      const double* vz = vs + face_off(slot, 2, nc);
+      const double lox = vx[g], loy = vy[g], loz = vz[g];
+      const double hix = (gx < m - 1) ? vx[g + 1] : 0.0;
+      const double hiy = (gy < m - 1) ? vy[g + m] : 0.0;
+      const double hiz = (gz < m - 1) ? vz[g + (int64_t)m * m] : 0.0;
+      const double fq = lox * (lox + 0.5 * hix) + loy * (loy + 0.5 * hiy) + loz * (loz + 0.5 * hiz);
+      const double dv = (hix - lox) + (hiy - loy) + (hiz - loz);
+      p_zv += z * (double)b[g];
+      p_azz += bxc.q * fq + 2.0 * z * bxc.h2q * dv - bxc.k2h3 * z * z;
+    }
+  }
+  if (FINE && part) {
+    p_zv = block_sum(p_zv, red);
+    p_azz = block_sum(p_azz, red);
+    if (threadIdx.x == 0) {
+      part[((int64_t)slot * nb + t) * 2 + 0] = p_zv;
+      part[((int64_t)slot * nb + t) * 2 + 1] = p_azz;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// multigrid: all levels from `top` down to 1^3 and back, in LDS, one block per
+// slot.  Each level keeps four arrays (b, x, y, t) of m^3 values.
+
+template <typename TM>
+__device__ __forceinline__ TM nsum(const TM* v, int x, int y, int z, int m, int c) {
+  TM s = 0;
+  if (x > 0) s += v[c - 1];
+  if (x < m - 1) s += v[c + 1];
+  if (y > 0) s += v[c - m];
+  if (y < m - 1) s += v[c + m];
+  if (z > 0) s += v[c - m * m];
+  if (z < m - 1) s += v[c + m * m];
+  return s;
+}
+
+template <typename TM>
+__global__ __launch_bounds__(kBlock) void k_mg_coarse(const TM* __restrict__ btop, TM* __restrict__ etop,
+                                                      CoarseParams P, const Scalars* __restrict__ sc) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TM* sm = reinterpret_cast<TM*>(smem_raw);
+  const int slot = blockIdx.x;
+  if (sc && sc[slot].state != ST_ACTIVE) return;
+  const int m0 = P.lv[0].m;
+  const int64_t nc0 = P.lv[0].nc;
+  {
+    TM* b = sm + P.off[0];
+    for (int c = threadIdx.x; c < nc0; c += kBlock) b[c] = btop[(int64_t)slot * nc0 + c];
+  }
+  __syncthreads();
+  for (int l = 0; l < P.nl - 1; ++l) {
+    const Level& L = P.lv[l];
+    const int m = L.m;
+    const int nc = (int)L.nc;
+    TM* b = sm + P.off[l];
+    TM* x = b + nc;
+    TM* y = x + nc;
+    TM* tt = y + nc;
+    const TM k2 = (TM)L.k2, a = (TM)L.a, c0 = (TM)L.c0, c1 = (TM)L.c1, c2 = (TM)L.c2;
+    for (int c = threadIdx.x; c < nc; c += kBlock) {
+      const int i = c % m, j = (c / m) % m, k = c / (m * m);
+      y[c] = c0 * b[c] / (k2 + a * (TM)nnbr(i, j, k, m));
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += kBlock) {
+      const int i = c % m, j = (c / m) % m, k = c / (m * m);
+      const TM d = k2 + a * (TM)nnbr(i, j, k, m);
+      const TM Ay = d * y[c] - a * nsum(y, i, j, k, m, c);
+      x[c] = c1 * y[c] + (c2 / d) * (b[c] - Ay);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += kBlock) {
+      const int i = c % m, j = (c / m) % m, k = c / (m * m);
+      const TM d = k2 + a * (TM)nnbr(i, j, k, m);
+      tt[c] = b[c] - (d * x[c] - a * nsum(x, i, j, k, m, c));
+    }
+    __syncthreads();
+    const int mh = m >> 1;
+    TM* bn = sm + P.off[l + 1];
+    for (int C = threadIdx.x; C < mh * mh * mh; C += kBlock) {
+      const int I = C % mh, J = (C / mh) % mh, K = C / (mh * mh);
+      TM acc = 0;
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch) {
+        const int i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
+        acc += tt[i + m * (j + m * k)];
+      }
+      bn[C] = acc;
+    }
+    __syncthreads();
+  }
+  {
+    const Level& L = P.lv[P.nl - 1];
+    const int m = L.m;
+    const int nc = (int)L.nc;
+    TM* b = sm + P.off[P.nl - 1];
+    TM* x = b + nc;
+    // coarsest level: a single cell, S~ = kappa^2 H^3 (no neighbours): exact
+    for (int c = threadIdx.x; c < nc; c += kBlock) {
+      const int i = c % m, j = (c / m) % m, k = c / (m * m);
+      x[c] = b[c] / ((TM)L.k2 + (TM)L.a * (TM)nnbr(i, j, k, m));
+    }
+    __syncthreads();
+  }
+  for (int l = P.nl - 2; l >= 0; --l) {
+    const Level& L = P.lv[l];
+    const int m = L.m;
+    const int nc = (int)L.nc;
+    const int mh = m >> 1;
+    TM* b = sm + P.off[l];
+    TM* x = b + nc;
+    TM* y = x + nc;
+    TM* tt = y + nc;
+    const TM* xn = sm + P.off[l + 1] + (int)P.lv[l + 1].nc;
+    const TM k2 = (TM)L.k2, a = (TM)L.a, c0 = (TM)L.c0, c1 = (TM)L.c1, c2 = (TM)L.c2;
+    for (int c = threadIdx.x; c < nc; c += kBlock) {
+      const int i = c % m, j = (c / m) % m, k = c / (m * m);
+      x[c] += xn[(i >> 1) + mh * ((j >> 1) + mh * (k >> 1))];
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += kBlock) {
+      const int i = c % m, j = (c / m) % m, k = c / (m * m);
+      const TM d = k2 + a * (TM)nnbr(i, j, k, m);
+      const TM r = b[c] - (d * x[c] - a * nsum(x, i, j, k, m, c));
+      tt[c] = r;
+      y[c] = c0 * r / d;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += kBlock) {
+      const int i = c % m, j = (c / m) % m, k = c / (m * m);
+      const TM d = k2 + a * (TM)nnbr(i, j, k, m);
+      const TM t2 = tt[c] - (d * y[c] - a * nsum(y, i, j, k, m, c));
+      x[c] += c1 * y[c] + (c2 / d) * t2;
+    }
+    __syncthreads();
+  }
+  {
+    const TM* x = sm + P.off[0] + nc0;
+    for (int c = threadIdx.x; c < nc0; c += kBlock) etop[(int64_t)slot * nc0 + c] = x[c];
+  }
+  (void)m0;
+}
+
+// ---------------------------------------------------------------------------
+// scalar step of iteration j (one block per slot)
+
+__global__ __launch_bounds__(kBlock) void k_scalar(Fields F, int nb_up, int nb_pb) {
+  __shared__ double red[kBlock / 64];
+  const int slot = blockIdx.x;
+  Scalars* S = F.sc + slot;
+  const int state = S->state;
+  if (state == ST_FINISH) {
+    if (threadIdx.x == 0) S->state = ST_DONE;
+    return;
+  }
+  if (state != ST_ACTIVE) return;
+  const int j = S->it;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  const double* pu = F.part_up + (int64_t)slot * nb_up * 2;
+  for (int i = threadIdx.x; i < nb_up; i += kBlock) { a0 += pu[2 * i]; a1 += pu[2 * i + 1]; }
+  if (j > 1) {
+    const double* pp = F.part_pb + (int64_t)slot * nb_pb;
+    for (int i = threadIdx.x; i < nb_pb; i += kBlock) a2 += pp[i];
+  }
+  a0 = block_sum(a0, red);
+  a1 = block_sum(a1, red);
+  a2 = block_sum(a2, red);
+  if (threadIdx.x != 0) return;
+
+  Scalars s = *S;
+  const double gg = a2 + a0;          // gamma_j^2
+  if (!(gg >= 0.0) || !isfinite(gg) || !isfinite(a1)) {
+    s.state = ST_FAILED; s.iters = j - 1; *S = s; return;
+  }
+  if (gg == 0.0 && j == 1) {           // zero right-hand side: the solution is 0
+    s.state = ST_DONE; s.flags |= FL_ZERO; s.iters = 0; *S = s; return;
+  }
+  const double gam = sqrt(gg);
+  const double del = gg > 0.0 ? a1 / gg : 0.0;
+  if (j == 1) {
+    s.eta = gam; s.eta0 = gam;
+    s.c = s.c_prev = 1.0; s.s = s.s_prev = 0.0;
+    s.wmode = -1;
+    s.b_v = 0.0;
+  } else {
+    // complete the Givens rotation of step j-1 now that gamma_j is known
+    const double dp = s.delta, gp = s.gamma;
+    const double al0 = s.c * dp - s.c_prev * s.s * gp;
+    const double al1 = sqrt(al0 * al0 + gg);
+    const double al2 = s.s * dp + s.c_prev * s.c * gp;
+    const double al3 = s.s_prev * gp;
+    if (!(al1 > 0.0) || !isfinite(al1)) { s.state = ST_FAILED; s.iters = j - 1; *S = s; return; }
+    const double cn = al0 / al1, sn = gam / al1;
+    s.wz = 1.0 / (al1 * gp);
+    s.ww_prev = -al3 / al1;
+    s.ww = -al2 / al1;
+    s.xw = cn * s.eta;
+    s.eta = -sn * s.eta;
+    s.c_prev = s.c; s.s_prev = s.s;
+    s.c = cn; s.s = sn;
+    s.wmode = (j == 2) ? 0 : ((j == 3) ? 1 : 2);
+    s.b_v = gam / gp;
+    if (fabs(s.eta) <= s.tol * s.eta0 || gg == 0.0) {
+      s.state = ST_FINISH; s.iters = j - 1;
+    } else if (j - 1 >= s.max_iter) {
+      s.state = ST_FINISH; s.iters = j - 1; s.flags |= FL_NOTCONV;
+    }
+  }
+  s.gamma_prev = (j == 1) ? 1.0 : s.gamma;
+  s.gamma = gam;
+  s.delta = del;
+  s.zs = gam > 0.0 ? 1.0 / gam : 0.0;
+  s.a_v = gam > 0.0 ? del / gam : 0.0;
+  s.pit = j;
+  s.it = j + 1;
+  *S = s;
+}
+
+// ---------------------------------------------------------------------------
+// operator pass of iteration j:
+//   v_{j+1} = A z_j - a_v v_j - b_v v_{j-1},  z_j = (q v_sigma, zhat_u) / gamma_j
+// and the delayed direction/solution update of step j-1.  One thread per
+// cell: the cell value and the three low faces of the cell.  With
+// z_sigma = q v_sigma, q h^3 = 3/2:
+//   (M z)_face = (v + (v_lo + v_hi) / 4) / gamma        (line tridiagonal)
+//   (B^T z_u)_face = h^2 (zhat[c - e_d] - zhat[c]) / gamma
+//   (A z)_cell = (h^2 q sum_d (v_hi - v_lo) - kappa^2 h^3 zhat) / gamma
+
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
+  __shared__ double red[kBlock / 64];
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int slot = lb / nb, blk = lb - slot * nb;
+  const Scalars* S = F.sc + slot;
+  const int state = S->state;
+  if (state != ST_ACTIVE && state != ST_FINISH) return;
+  const int j = S->pit;
+  const int p = j & 1, pq = p ^ 1;
+  const int64_t nc = bx.nc;
+  const int n = bx.n;
+  const int64_t n2 = bx.n2;
+  const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
+  double ssig = 0.0;
+  if (c < nc) {
+    const int i = (int)(c % n), jj = (int)((c / n) % n), k = (int)(c / n2);
+    const int64_t co = cell_off(slot, nc);
+    if (state == ST_ACTIVE) {
+      const double zs = S->zs, av = S->a_v, bv = S->b_v;
+      const bool has_prev = j > 1;
+      const double* vx = F.vs[p] + face_off(slot, 0, nc);
+      const double* vy = F.vs[p] + face_off(slot, 1, nc);
+      const double* vz = F.vs[p] + face_off(slot, 2, nc);
+      const TZ* z = reinterpret_cast<const TZ*>(F.z[p]) + co;
+      const double zc = (double)z[c];
+      const double vxc = vx[c], vyc = vy[c], vzc = vz[c];
+      const double vxh = (i < n - 1) ? vx[c + 1] : 0.0;
+      const double vyh = (jj < n - 1) ? vy[c + n] : 0.0;
+      const double vzh = (k < n - 1) ? vz[c + n2] : 0.0;
+      const double Au = zs * (bx.h2q * ((vxh - vxc) + (vyh - vyc) + (vzh - vzc)) - bx.k2h3 * zc);
+      double Ax = 0.0, Ay = 0.0, Az = 0.0;
+      if (i > 0) Ax = zs * (vxc + 0.25 * (vx[c - 1] + vxh) + bx.h2 * ((double)z[c - 1] - zc));
+      if (jj > 0) Ay = zs * (vyc + 0.25 * (vy[c - n] + vyh) + bx.h2 * ((double)z[c - n] - zc));
+      if (k > 0) Az = zs * (vzc + 0.25 * (vz[c - n2] + vzh) + bx.h2 * ((double)z[c - n2] - zc));
+      double* ox = F.vs[pq] + face_off(slot, 0, nc);
+      double* oy = F.vs[pq] + face_off(slot, 1, nc);
+      double* oz = F.vs[pq] + face_off(slot, 2, nc);
+      double* ou = F.vu[pq] + co;
+      double nu = Au - av * F.vu[p][co + c];
+      double nx = Ax - av * vxc, ny = Ay - av * vyc, nz = Az - av * vzc;
+      if (has_prev) {
+        nu -= bv * ou[c];
+        nx -= bv * ox[c];
+        ny -= bv * oy[c];
+        nz -= bv * oz[c];
+      }
+      if (i == 0) nx = 0.0;
+      if (jj == 0) ny = 0.0;
+      if (k == 0) nz = 0.0;
+      ou[c] = nu; ox[c] = nx; oy[c] = ny; oz[c] = nz;
+      ssig = bx.q * (nx * nx + ny * ny + nz * nz);
+    }
+    const int wm = S->wmode;
+    if (wm >= 0) {
+      // w_j = wz zhat_{j-1} + ww_prev w_{j-2} + ww w_{j-1};  x_{j-1} = x_{j-2} + xw w_j
+      const TZ* zp = reinterpret_cast<const TZ*>(F.z[pq]) + co;
+      double* wj = F.w[p] + co;          // holds w_{j-2}, receives w_j
+      const double* w1 = F.w[pq] + co;   // w_{j-1}
+      double wn = S->wz * (double)zp[c];
+      if (wm >= 1) wn += S->ww * w1[c];
+      if (wm >= 2) wn += S->ww_prev * wj[c];
+      wj[c] = wn;
+      double* x = F.x + co;
+      x[c] = (wm == 0) ? S->xw * wn : x[c] + S->xw * wn;
+    }
+  }
+  if (state == ST_ACTIVE) {
+    ssig = block_sum(ssig, red);
+    if (threadIdx.x == 0) F.part_pb[(int64_t)slot * nb + blk] = ssig;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// finishing
+
+// Zero / NaN the solution of slots that finished with FL_ZERO / ST_FAILED.
+__global__ __launch_bounds__(kBlock) void k_fix_solution(Fields F, Box bx, int nb) {
+  const int slot = blockIdx.x / nb, blk = blockIdx.x - slot * nb;
+  const Scalars* S = F.sc + slot;
+  const bool zero = S->flags & FL_ZERO;
+  const bool fail = S->state == ST_FAILED;
+  if (!zero && !fail) return;
+  const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
+  if (c < bx.nc) F.x[cell_off(slot, bx.nc) + c] = zero ? 0.0 : __builtin_nan("");
+}
+
+// Flux recovery sigma = -M^-1 B^T u (first block row of eq. linsys): along
+// each grid line, tridiag(1/6, 2/3, 1/6) sigma = (u_c - u_{c-1}) / h over the
+// n-1 interior faces (Thomas algorithm; one thread per line).  Writes the
+// internal face layout (sig_int [slot][3][n^3], may be null) and the external
+// layout (sig_ext [slot][3 n^2 (n+1)], may be null).
+__global__ __launch_bounds__(kBlock) void k_flux(const double* __restrict__ u, double* __restrict__ sig_int,
+                                                 double* __restrict__ sig_ext, Box bx, int batch) {
+  __shared__ double cp[1024];
+  const int n = bx.n;
+  // c'_i of the forward sweep (identical for every line)
+  if (threadIdx.x == 0) {
+    double cprev = 0.0;
+    for (int i = 1; i < n; ++i) {
+      const double mdiag = (2.0 / 3.0) - (1.0 / 6.0) * cprev;
+      cprev = (1.0 / 6.0) / mdiag;
+      cp[i] = cprev;
+    }
+  }
+  __syncthreads();
+  const int64_t lines = 3 * bx.n2;
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= lines * batch) return;
+  const int slot = (int)(gid / lines);
+  const int64_t l = gid - (int64_t)slot * lines;
+  const int d = (int)(l / bx.n2);
+  const int64_t rest = l - (int64_t)d * bx.n2;
+  const int64_t nc = bx.nc;
+  const double* us = u + cell_off(slot, nc);
+  // line coordinates: the two indices other than d, fastest first
+  const int a = (int)(rest % n), b = (int)(rest / n);
+  int64_t base, stride;
+  if (d == 0) { base = (int64_t)n * (a + (int64_t)n * b); stride = 1; }
+  else if (d == 1) { base = a + (int64_t)n * n * b; stride = n; }
+  else { base = a + (int64_t)n * b; stride = bx.n2; }
+  const double inv_h = 1.0 / bx.h;
+  double* si = sig_int ? sig_int + face_off(slot, d, nc) : nullptr;
+  double* se = nullptr;
+  int64_t ebase = 0, estride = 0;
+  if (sig_ext) {
+    const int64_t nf = bx.n2 * (n + 1);
+    se = sig_ext + (int64_t)slot * 3 * nf + (int64_t)d * nf;
+    if (d == 0) { ebase = (int64_t)(n + 1) * (a + (int64_t)n * b); estride = 1; }
+    else if (d == 1) { ebase = a + (int64_t)n * (n + 1) * b; estride = n; }
+    else { ebase = a + (int64_t)n * b; estride = bx.n2; }
+  }
+  // forward sweep: store d'_i in the output (internal if present, else external)
+  double dprev = 0.0;
+  double* tmp = si ? si : se;
+  const int64_t tb = si ? base : ebase;
+  const int64_t ts = si ? stride : estride;
+  for (int i = 1; i < n; ++i) {
+    const double rhs = (us[base + (int64_t)i * stride] - us[base + (int64_t)(i - 1) * stride]) * inv_h;
+    const double mdiag = (2.0 / 3.0) - (1.0 / 6.0) * (i > 1 ? cp[i - 1] : 0.0);
+    dprev = (rhs - (1.0 / 6.0) * dprev) / mdiag;
+    tmp[tb + (int64_t)i * ts] = dprev;
+  }
+  double snext = 0.0;
+  for (int i = n - 1; i >= 1; --i) {
+    const double sv = tmp[tb + (int64_t)i * ts] - (i < n - 1 ? cp[i] * snext : 0.0);
+    snext = sv;
+    if (si) si[base + (int64_t)i * stride] = sv;
+    if (se) se[ebase + (int64_t)i * estride] = sv;
+  }
+  if (si) si[base] = 0.0;
+  if (se) { se[ebase] = 0.0; se[ebase + (int64_t)n * estride] = 0.0; }
+}
+
+// True residual of the cell row with the recovered flux:
+//   r = F_u - (B sigma - kappa^2 h^3 u),  F_u = -g h^{3/2} xi.
+// Per-block partial sums of |r|^2 and |F_u|^2.
+__global__ __launch_bounds__(kBlock) void k_resid(const double* __restrict__ sig, const double* __restrict__ u,
+                                                  const double* __restrict__ xi, double scale, Box bx,
+                                                  int nb, double* __restrict__ part) {
+  __shared__ double red[kBlock / 64];
+  const int slot = blockIdx.x / nb, blk = blockIdx.x - slot * nb;
+  const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
+  const int64_t nc = bx.nc;
+  const int n = bx.n;
+  double rr = 0.0, ff = 0.0;
+  if (c < nc) {
+    const int i = (int)(c % n), j = (int)((c / n) % n), k = (int)(c / bx.n2);
+    const double* sx = sig + face_off(slot, 0, nc);
+    const double* sy = sig + face_off(slot, 1, nc);
+    const double* sz = sig + face_off(slot, 2, nc);
+    const double div = ((i < n - 1 ? sx[c + 1] : 0.0) - sx[c]) + ((j < n - 1 ? sy[c + n] : 0.0) - sy[c]) +
+                       ((k < n - 1 ? sz[c + bx.n2] : 0.0) - sz[c]);
+    const double uc = u[cell_off(slot, nc) + c];
+    const double fu = scale * xi[cell_off(slot, nc) + c];
+    const double r = fu - (bx.h2 * div - bx.k2h3 * uc);
+    rr = r * r;
+    ff = fu * fu;
+  }
+  rr = block_sum(rr, red);
+  ff = block_sum(ff, red);
+  if (threadIdx.x == 0) {
+    part[((int64_t)slot * nb + blk) * 2 + 0] = rr;
+    part[((int64_t)slot * nb + blk) * 2 + 1] = ff;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_resid_reduce(const double* __restrict__ part, int nb,
+                                                         double* __restrict__ out) {
+  __shared__ double red[kBlock / 64];
+  const int slot = blockIdx.x;
+  double rr = 0.0, ff = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) {
+    rr += part[((int64_t)slot * nb + i) * 2];
+    ff += part[((int64_t)slot * nb + i) * 2 + 1];
+  }
+  rr = block_sum(rr, red);
+  ff = block_sum(ff, red);
+  if (threadIdx.x == 0) out[slot] = ff > 0.0 ? sqrt(rr / ff) : sqrt(rr);
+}
+
+// ---------------------------------------------------------------------------
+// transfer: u_tet = Pi u (CSR, one thread per tet row, NR samples per pass)
+
+template <int NR>
+__global__ __launch_bounds__(kBlock) void k_spmm(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                 const double* __restrict__ cv, const double* __restrict__ u,
+                                                 double* __restrict__ out, int64_t ntet, int64_t nnz, int64_t nc,
+                                                 int batch) {
+  const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int s0 = blockIdx.y * NR;
+  if (row >= ntet) return;
+  const int nr = min(NR, batch - s0);
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+  // row bounds and column indices come from the caller: clamp them so that a
+  // malformed matrix cannot read outside its arrays or the box field
+  const int64_t k0 = max((int64_t)0, min(rp[row], nnz)), k1 = max(k0, min(rp[row + 1], nnz));
+  for (int64_t k = k0; k < k1; ++k) {
+    const int64_t col = ci[k];
+    if (col < 0 || col >= nc) continue;
+    const double v = cv[k];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (r < nr) acc[r] += v * u[(int64_t)(s0 + r) * nc + col];
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    if (r < nr) out[(int64_t)(s0 + r) * ntet + row] = acc[r];
+}
+
+// ---------------------------------------------------------------------------
+// noise restriction (eq. ml-linsys): xi_c[I] = 8^{-1/2} sum of the 8 children
+
+__global__ __launch_bounds__(kBlock) void k_restrict_noise(const double* __restrict__ xf, double* __restrict__ xc,
+                                                           int nf, int batch) {
+  const int ncx = nf >> 1;
+  const int64_t ncc = (int64_t)ncx * ncx * ncx;
+  const int64_t nff = (int64_t)nf * nf * nf;
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= ncc * batch) return;
+  const int slot = (int)(gid / ncc);
+  const int64_t C = gid - (int64_t)slot * ncc;
+  const int I = (int)(C % ncx), J = (int)((C / ncx) % ncx), K = (int)(C / ((int64_t)ncx * ncx));
+  const double* f = xf + (int64_t)slot * nff;
+  double acc = 0.0;
+#pragma unroll
+  for (int ch = 0; ch < 8; ++ch) {
+    const int i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
+    acc += f[i + (int64_t)nf * (j + (int64_t)nf * k)];
+  }
+  xc[gid] = acc * 0.35355339059327376220;   // 1 / sqrt(8)
+}
+
+// ---------------------------------------------------------------------------
+// layout conversions for the operator check: external -> internal Lanczos form
+// (v_sigma = x_sigma / q so that q v_sigma = x_sigma, zhat = x_u), and back.
+
+__global__ __launch_bounds__(kBlock) void k_ext_to_int(const double* __restrict__ xs, const double* __restrict__ xu,
+                                                       Fields F, Box bx, int nb) {
+  const int slot = blockIdx.x / nb, blk = blockIdx.x - slot * nb;
+  const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
+  const int64_t nc = bx.nc;
+  const int n = bx.n;
+  if (c >= nc) return;
+  const int i = (int)(c % n), j = (int)((c / n) % n), k = (int)(c / bx.n2);
+  const int64_t nf = bx.n2 * (n + 1);
+  const double* e = xs + (int64_t)slot * 3 * nf;
+  const double iq = 1.0 / bx.q;
+  F.vs[0][face_off(slot, 0, nc) + c] = i > 0 ? e[i + (int64_t)(n + 1) * (j + (int64_t)n * k)] * iq : 0.0;
+  F.vs[0][face_off(slot, 1, nc) + c] = j > 0 ? e[nf + i + (int64_t)n * (j + (int64_t)(n + 1) * k)] * iq : 0.0;
+  F.vs[0][face_off(slot, 2, nc) + c] = k > 0 ? e[2 * nf + i + (int64_t)n * (j + (int64_t)n * k)] * iq : 0.0;
+  reinterpret_cast<double*>(F.z[0])[cell_off(slot, nc) + c] = xu[cell_off(slot, nc) + c];
+  F.vu[0][cell_off(slot, nc) + c] = 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_int_to_ext(Fields F, double* __restrict__ ys, double* __restrict__ yu,
+                                                       Box bx, int nb) {
+  const int slot = blockIdx.x / nb, blk = blockIdx.x - slot * nb;
+  const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
+  const int64_t nc = bx.nc;
+  const int n = bx.n;
+  if (c >= nc) return;
+  const int i = (int)(c % n), j = (int)((c / n) % n), k = (int)(c / bx.n2);
+  const int64_t nf = bx.n2 * (n + 1);
+  double* e = ys + (int64_t)slot * 3 * nf;
+  e[i + (int64_t)(n + 1) * (j + (int64_t)n * k)] = F.vs[1][face_off(slot, 0, nc) + c];
+  e[nf + i + (int64_t)n * (j + (int64_t)(n + 1) * k)] = F.vs[1][face_off(slot, 1, nc) + c];
+  e[2 * nf + i + (int64_t)n * (j + (int64_t)n * k)] = F.vs[1][face_off(slot, 2, nc) + c];
+  if (i == n - 1) e[n + (int64_t)(n + 1) * (j + (int64_t)n * k)] = 0.0;
+  if (j == n - 1) e[nf + i + (int64_t)n * (n + (int64_t)(n + 1) * k)] = 0.0;
+  if (k == n - 1) e[2 * nf + i + (int64_t)n * (j + (int64_t)n * n)] = 0.0;
+  yu[cell_off(slot, nc) + c] = F.vu[1][cell_off(slot, nc) + c];
+}
+
+// Scalars of the operator check: z = (q v, zhat) / 1, no recurrence terms.
+__global__ void k_probe_scalars(Scalars* sc, int batch) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= batch) return;
+  Scalars v{};
+  v.state = ST_ACTIVE; v.pit = 0; v.it = 0; v.zs = 1.0; v.a_v = 0.0; v.b_v = 0.0; v.wmode = -1;
+  sc[s] = v;
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(kBlock) void k_convert(const TS* __restrict__ s, TD* __restrict__ d, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < count) d[i] = (TD)s[i];
+}
+
+}  // namespace spde
+
+#include "spde_launch.inc"

@@ -1,0 +1,176 @@
+"""GPU parity of the HIP path against the CPU oracle (run with -m gpu on an MI355X).
+
+Bars (per sample, relative L2 on box cells): <= 1e-10 in float64 mode,
+<= 1e-7 in mixed mode; the operator apply and the transfer SpMM to ~1e-13.
+"""
+import numpy as np
+import pytest
+
+from oracle import discretize as D, noise, spectral as S, transfer as T
+from tests.gpu_common import gval, oracle_apply_full, oracle_u, rel_l2, say
+from workloads import WORKLOADS, tet_mesh, xi_batch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def P():
+    import paper_1712_06758_amd as P_
+    return P_
+
+
+@pytest.mark.parametrize("n,batch", [(4, 1), (8, 3), (16, 2)])
+def test_operator_matches_oracle_matrix(torch_cuda, n, batch):
+    torch = torch_cuda
+    say(f"operator n={n} batch={batch}")
+    kappa = 7.0
+    box = P().Box(n, kappa, precision="fp64", max_batch=batch)
+    rng = np.random.default_rng(n)
+    nf = D.counts(n)[1]
+    xs = rng.standard_normal((batch, nf))
+    xu = rng.standard_normal((batch, n ** 3))
+    ys, yu = box.apply_operator(torch.tensor(xs, device="cuda"), torch.tensor(xu, device="cuda"))
+    torch.cuda.synchronize()
+    rs, ru = oracle_apply_full(n, kappa, xs, xu)
+    ys = ys.cpu().numpy(); yu = yu.cpu().numpy()
+    assert np.abs(ys - rs).max() <= 1e-13 * np.abs(rs).max()
+    assert np.abs(yu - ru).max() <= 1e-13 * np.abs(ru).max()
+
+
+@pytest.mark.parametrize("prec,n", [("fp64", 16), ("fp64", 32), ("mixed", 32)])
+def test_vcycle_symmetric_positive(torch_cuda, prec, n):
+    torch = torch_cuda
+    say(f"vcycle {prec} n={n}")
+    box = P().Box(n, 10.0, precision=prec, max_batch=2)
+    rng = np.random.default_rng(3)
+    r = torch.tensor(rng.standard_normal((2, n ** 3)), device="cuda")
+    z = box.apply_vcycle(r)
+    torch.cuda.synchronize()
+    r = r.cpu().numpy(); z = z.cpu().numpy()
+    a = float(r[0] @ z[1]); b = float(r[1] @ z[0])
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert abs(a - b) <= tol * np.sqrt((r[0] @ z[0]) * (r[1] @ z[1]))
+    assert r[0] @ z[0] > 0 and r[1] @ z[1] > 0
+
+
+def _run_sample(torch, n, kappa, prec, xi, mesh=None, **kw):
+    box = P().Box(n, kappa, precision=prec, max_batch=xi.shape[0])
+    if mesh is not None:
+        box.set_mesh(*mesh)
+    out = box.sample(torch.tensor(xi, device="cuda"), u_box=True, **kw)
+    torch.cuda.synchronize()
+    return box, out
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-10), ("mixed", 1e-7)])
+def test_box16_single_sample(torch_cuda, prec, bar):
+    """16^3 box, one noise vector (seed 0), rotated 6,000-tet mesh of [0.2,0.8]^3."""
+    torch = torch_cuda
+    w = WORKLOADS["box16"]
+    say(f"box16 {prec}")
+    xi = w.noise()
+    xyz, tets = w.mesh()
+    box, out = _run_sample(torch, w.n, w.kappa, prec, xi, mesh=(xyz, tets), sigma=True, relres=True)
+    u_ref = oracle_u(w.n, w.kappa, w.g, xi)
+    u = out["u_box"].cpu().numpy()
+    err = rel_l2(u[0], u_ref[0])
+    say(f"box16 {prec}: iters={out['iters'].tolist()} rel_err={err:.3e} relres={out['relres'].tolist()}")
+    assert err <= bar
+    # flux from the oracle's u
+    ops = D.assemble(w.n)
+    s_ref = D.full_faces(ops, S.flux_from_u(ops, u_ref[0]))
+    assert rel_l2(out["sigma"].cpu().numpy()[0], s_ref) <= 10 * bar
+    assert out["relres"][0] <= (1e-9 if prec == "fp64" else 1e-6)
+    # transfer rows: oracle overlap volumes on 300 sampled tets
+    ut = out["u_tet"].cpu().numpy()[0]
+    rows = np.random.default_rng(5).choice(tets.shape[0], 300, replace=False)
+    Pi = T.build_pi(xyz, tets, w.n, rows=rows)
+    ref = Pi @ u_ref[0]
+    assert np.abs(ut[rows] - ref).max() <= 10 * bar * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-10), ("mixed", 1e-7)])
+def test_box64_batch(torch_cuda, prec, bar):
+    """64^3 box, 8 of the 32 seeded noise vectors in one launch."""
+    torch = torch_cuda
+    w = WORKLOADS["box64"]
+    say(f"box64 {prec} batch=8")
+    xi = w.noise(8)
+    box, out = _run_sample(torch, w.n, w.kappa, prec, xi)
+    u = out["u_box"].cpu().numpy()
+    u_ref = oracle_u(w.n, w.kappa, w.g, xi)
+    errs = [rel_l2(u[b], u_ref[b]) for b in range(xi.shape[0])]
+    say(f"box64 {prec}: iters={out['iters'].tolist()} max_err={max(errs):.3e}")
+    assert max(errs) <= bar
+
+
+def test_batch_invariance_bitwise(torch_cuda):
+    """A noise vector gives bitwise the same field alone and at slot 3 of 5."""
+    torch = torch_cuda
+    say("batch invariance n=32")
+    n, kappa = 32, 20.0
+    xi = xi_batch(n, [11, 12, 13, 14, 15])
+    _, alone = _run_sample(torch, n, kappa, "fp64", xi[3:4])
+    _, mix = _run_sample(torch, n, kappa, "fp64", xi)
+    assert torch.equal(alone["u_box"][0], mix["u_box"][3])
+    assert alone["iters"][0] == mix["iters"][3]
+
+
+def test_graphs_match_plain_launches(torch_cuda):
+    torch = torch_cuda
+    say("graphs vs plain n=16")
+    n, kappa = 16, 10.0
+    xi = torch.tensor(xi_batch(n, [1, 2]), device="cuda")
+    box = P().Box(n, kappa, max_batch=2)
+    a = box.sample(xi, u_box=True)["u_box"].clone()
+    box.set_graphs(False)
+    b = box.sample(xi, u_box=True)["u_box"].clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_zero_and_nan_noise(torch_cuda):
+    torch = torch_cuda
+    say("zero / nan noise n=8")
+    import paper_1712_06758_amd as PP
+    n, kappa = 8, 10.0
+    xi = xi_batch(n, [0, 1, 2])
+    xi[0] = 0.0
+    xi[2, 5] = np.nan
+    box = PP.Box(n, kappa, max_batch=3)
+    with pytest.raises(PP.SpdeError) as ei:
+        box.sample(torch.tensor(xi, device="cuda"), u_box=True)
+    assert ei.value.status == PP.SPDE_EFAILED
+    # the same batch without the NaN: zero noise gives an exactly zero field
+    xi[2, 5] = 0.1
+    out = box.sample(torch.tensor(xi, device="cuda"), u_box=True)
+    u = out["u_box"].cpu().numpy()
+    assert np.all(u[0] == 0.0)
+    assert rel_l2(u[1], oracle_u(n, kappa, gval(kappa), xi[1:2])[0]) <= 1e-10
+
+
+def test_max_iter_reports_notconv(torch_cuda):
+    torch = torch_cuda
+    say("max_iter=3 n=16")
+    import paper_1712_06758_amd as PP
+    box = PP.Box(16, 10.0, max_iter=3)
+    out = box.sample(torch.tensor(xi_batch(16, [0]), device="cuda"), u_box=True, allow_notconv=True)
+    assert out["status"] == PP.SPDE_ENOTCONV
+    assert out["iters"][0] == 3
+    assert np.all(np.isfinite(out["u_box"].cpu().numpy()))
+
+
+def test_restrict_noise_matches_oracle(torch_cuda):
+    torch = torch_cuda
+    say("restrict noise n=32 batch=3")
+    import paper_1712_06758_amd as PP
+    xi = xi_batch(32, [4, 5, 6])
+    xc = PP.restrict_noise(torch.tensor(xi, device="cuda"), 32).cpu().numpy()
+    ref = noise.restrict_batch(32, xi)
+    assert np.abs(xc - ref).max() <= 4e-16 * np.abs(ref).max()
