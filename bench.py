@@ -1,0 +1,232 @@
+"""Benchmark: SPDE field samples/s at 128^3 on one MI355X.
+
+A step is one call of the whole sampling path on one batch: noise -> RT0/P0
+mixed solve by block-preconditioned MINRES with a multigrid V-cycle -> L2
+projection onto the 2,431,344-tet mesh.  Inputs are resident in HBM before
+the timed region.  The headline value is the batched mixed-precision rate
+(64 right-hand sides per launch, float32 V-cycle inside float64 MINRES); the
+plain float64 rates (batch 64 and batch 1) are reported beside it.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("spde_kernels.hip", "spde_launch.inc", "spde_internal.h"):
+        with open(os.path.join(ROOT, "paper_1712_06758_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def time_steps(torch, box, xi, steps, warmup, timing=False):
+    for _ in range(warmup):
+        box.sample(xi)
+    torch.cuda.synchronize()
+    if timing:
+        box.timing(-1)
+        box.timing(1)
+    iters = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = box.sample(xi)
+        iters.append(out["iters"].copy())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rep = None
+    if timing:
+        box.timing(0)
+        rep = box.timing_report()
+    return (t1 - t0) / steps, np.concatenate(iters), rep
+
+
+def roofline_from(rep, traffic):
+    # dominant kernel by total time inside the timed region
+    name, r = max(rep.items(), key=lambda kv: kv[1]["total_ms"])
+    avg_ms = r["total_ms"] / r["launches"]
+    achieved = r["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    tr = None
+    if traffic and traffic.get("kernel") == name:
+        tr = traffic.get("bytes_per_launch")
+    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": tr,
+            "avg_ms": round(avg_ms, 4), "bytes_per_launch": r["bytes_per_launch"]}
+
+
+def vcycle_gbs(rep):
+    ms = sum(rep[k]["total_ms"] for k in rep if k.startswith("mg_"))
+    by = sum(rep[k]["bytes_per_launch"] * rep[k]["launches"] for k in rep if k.startswith("mg_"))
+    return round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 else None
+
+
+def cpu_baseline(n, kappa, g, xi_np, count):
+    """The oracle (spectral exact solve) on `count` right-hand sides of the workload."""
+    import oracle
+    t0 = time.perf_counter()
+    for b in range(count):
+        oracle.sample_box(n, kappa, g, xi_np[b])
+    dt = time.perf_counter() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return {"value": round(count / dt, 4), "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"{count} of the 64 noise vectors of the 128^3 workload through the oracle's "
+                      f"exact spectral box solve (scipy.fft, workers=-1); {dt:.1f} s of CPU time; the "
+                      f"transfer apply (<1% of the work) not included"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-mesh", action="store_true", help="skip the tet transfer (solve only)")
+    ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
+                    help="time one precision only (profiling runs)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this sampler runs on one GPU; multi-GPU runs are not part of this build",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_1712_06758_amd as P
+    from workloads import WORKLOADS, Workload
+
+    w = WORKLOADS["box128"]
+    if args.n != 128 or args.batch != 64:
+        w = Workload(f"box{args.n}", args.n, w.corr_len, args.batch, w.mesh_lo, w.mesh_hi,
+                     max(2, round(w.mesh_m * args.n / 128)), 0.0)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    if args.calib_copy_mib:
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calib_copy_mib} MiB done")
+        del src, dst
+    log(f"workload {w.name}: n={w.n} batch={w.batch} kappa={w.kappa} g={w.g:.4f}")
+    t0 = time.perf_counter()
+    xi_np = w.noise()
+    xi = torch.tensor(xi_np, device=dev)
+    log(f"noise generated in {time.perf_counter() - t0:.1f} s")
+
+    mesh = None if args.no_mesh else w.mesh()
+    results = {}
+    setup = {}
+    for prec in ((args.only,) if args.only else ("mixed", "fp64")):
+        box = P.Box(w.n, w.kappa, w.g, precision=prec, max_batch=w.batch, device=dev)
+        if mesh is not None:
+            t0 = time.perf_counter()
+            nt, nnz = box.set_mesh(*mesh)
+            setup["transfer_build_s"] = round(time.perf_counter() - t0, 2)
+            setup["n_tet"], setup["nnz"] = int(nt), int(nnz)
+        log(f"{prec}: timing batch {w.batch}")
+        dt, iters, rep = time_steps(torch, box, xi, args.steps, args.warmup, timing=True)
+        results[prec] = {"s_per_step": dt, "samples_per_s": w.batch / dt, "iters_mean": float(iters.mean()),
+                         "iters_max": int(iters.max()), "report": rep}
+        log(f"{prec}: {w.batch / dt:.1f} samples/s, {dt * 1e3:.1f} ms/step, iters {iters.mean():.1f}, "
+            f"info {box.info()}")
+        for k, v in sorted(rep.items(), key=lambda kv: -kv[1]["total_ms"]):
+            avg = v["total_ms"] / v["launches"]
+            gbs = v["bytes_per_launch"] / (avg * 1e-3) / 1e9 if v["bytes_per_launch"] else 0.0
+            log(f"   {k:14s} {v['total_ms'] / args.steps:9.2f} ms/step  {v['launches']:6d} launches  "
+                f"avg {avg:8.4f} ms  {gbs:8.1f} GB/s")
+        if args.only:
+            results[prec]["batch1_samples_per_s"] = float("nan")
+            del box
+            continue
+        # batch of one, same path
+        x1 = xi[:1].contiguous()
+        b1_steps = max(3, args.steps // 2)
+        dt1, it1, _ = time_steps(torch, box, x1, b1_steps, 1)
+        results[prec]["batch1_samples_per_s"] = 1.0 / dt1
+        log(f"{prec}: batch 1: {1.0 / dt1:.1f} samples/s")
+        info = box.info()
+        results[prec]["info"] = info
+        del box
+        torch.cuda.empty_cache()
+
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as fh:
+            t = json.load(fh)
+        if t.get("source_hash") == kernel_source_hash():
+            traffic = t
+
+    if args.only:
+        r = results[args.only]
+        print(json.dumps({"mode": "profile", "precision": args.only, "samples_per_s": r["samples_per_s"]}))
+        return
+    mx = results["mixed"]
+    fp = results["fp64"]
+    roof = roofline_from(mx["report"], traffic.get("mixed") if traffic else None)
+    line = {
+        "metric": "field samples/s at 128^3 (batched mixed precision, whole path: solve + projection)",
+        "value": round(mx["samples_per_s"], 2),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mx["s_per_step"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 MINRES + f32 multigrid",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.n}^3 box on [0,1]^3, lambda={w.corr_len}, kappa={w.kappa}, "
+                               f"batch {w.batch} seeded N(0,1) noise vectors, transfer to "
+                               f"{setup.get('n_tet', 0)}-tet jittered Kuhn mesh of [0.1,0.9]^3",
+                   "n": w.n, "batch": w.batch, "rtol_mixed": 1e-8, "rtol_fp64": 3e-11},
+        "fp64_samples_per_s": round(fp["samples_per_s"], 2),
+        "fp64_batch1_samples_per_s": round(fp["batch1_samples_per_s"], 2),
+        "mixed_batch1_samples_per_s": round(mx["batch1_samples_per_s"], 2),
+        "mixed_over_fp64": round(mx["samples_per_s"] / fp["samples_per_s"], 3),
+        "batched_mixed_over_plain_fp64_batch1": round(mx["samples_per_s"] / fp["batch1_samples_per_s"], 3),
+        "iterations": {"mixed": mx["iters_mean"], "fp64": fp["iters_mean"]},
+        "vcycle_hbm_gbs": {"mixed": vcycle_gbs(mx["report"]), "fp64": vcycle_gbs(fp["report"])},
+        "roofline": roof,
+        "roofline_fp64": roofline_from(fp["report"], traffic.get("fp64") if traffic else None),
+        "kernels": {p: {k: {"avg_ms": round(v["total_ms"] / v["launches"], 4),
+                            "gbs": round(v["bytes_per_launch"] / (v["total_ms"] / v["launches"] * 1e-3) / 1e9, 1)
+                            if v["bytes_per_launch"] else None}
+                        for k, v in results[p]["report"].items()} for p in results},
+        "setup": setup,
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(w.n, w.kappa, w.g, xi_np, 4)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -107,7 +107,7 @@ spde_status spde_bind_workspace(spde_handle h, void* dev_ptr, size_t bytes);
  *   *row_ptr_host [n_tet+1] int64, *col_host [nnz] int32 (ascending per row),
  *   *val_host [nnz] float64; release each with spde_free_host().
  * Returns SPDE_EINVAL for a vertex outside [0,1]^3, a degenerate tet or an
- * index out of range.  Host-only; uses all OpenMP threads. */
+ * index out of range.  Host-only; runs on all hardware threads. */
 spde_status spde_build_transfer(spde_handle h, int64_t n_vert, const double* xyz_host,
                                 int64_t n_tet, const int32_t* tet_host,
                                 int64_t** row_ptr_host, int32_t** col_host,
@@ -174,6 +174,25 @@ spde_status spde_apply_transfer(spde_handle h, int batch, const double* u_box_de
 /* Replay MINRES iterations from captured HIP graphs (1, default) or launch
  * kernels one by one (0).  Results are bitwise identical either way. */
 spde_status spde_set_graphs(spde_handle h, int enable);
+
+/* Autotuning of the multigrid tile shapes (default on).  When on, the first
+ * sample or V-cycle call of a handle times every admissible tile shape of each
+ * per-level kernel at max_batch and keeps the fastest; the choice is shared by
+ * all handles of the process with the same device architecture, n and
+ * precision, and is appended to the file named by the environment variable
+ * SPDE_TUNE_CACHE (if set), from which later processes read it.  Off: fixed
+ * default tiles.  Results depend on the tiles only through the rounding of
+ * per-block partial sums (a few ulps). */
+spde_status spde_set_autotune(spde_handle h, int enable);
+
+/* Tile shape ids of the per-level multigrid kernels (level 0 = finest):
+ *   3-D tiles (x*y*z cells):   0: 16x8x8  1: 8x8x8  2: 32x8x4  3: 16x16x4
+ *                              4: 32x4x4  5: 16x8x4  (float64 up-kernels: 1, 4, 5 only)
+ *   2.5-D columns x planes:    6: 32x8 x 32  7: 16x16 x 32  8: 32x8 x 16  9: 32x8 x 64
+ * spde_set_tiles fixes the shapes of one level (or all levels with level = -1)
+ * and turns autotuning off for the handle; spde_get_tiles reads them. */
+spde_status spde_set_tiles(spde_handle h, int level, int down_shape, int up_shape);
+spde_status spde_get_tiles(spde_handle h, int level, int* down_shape, int* up_shape);
 
 /* Iterations per convergence poll (default 8; 1..256). */
 spde_status spde_set_poll_interval(spde_handle h, int iters);

@@ -175,7 +175,7 @@ class Box:
         iters = np.zeros(B, dtype=np.int32)
         rel = np.zeros(B, dtype=np.float64) if relres else None
         with torch.cuda.device(self.device):
-            st = self._hh and _abi.lib().spde_sample(
+            st = _abi.lib().spde_sample(
                 self._hh.h, B, _ptr(xi), _ptr(t_tet), _ptr(t_box), _ptr(t_sig), _stream_ptr(self.device),
                 iters.ctypes.data_as(C.c_void_p),
                 rel.ctypes.data_as(C.c_void_p) if rel is not None else None)
@@ -233,6 +233,18 @@ class Box:
     def set_poll_interval(self, k: int):
         _abi.check(_abi.lib().spde_set_poll_interval(self._hh.h, int(k)))
 
+    def set_autotune(self, enable: bool):
+        _abi.check(_abi.lib().spde_set_autotune(self._hh.h, int(bool(enable))))
+
+    def set_tiles(self, down: int, up: int, level: int = -1):
+        """Fix the multigrid tile shapes (ids 0..9) of one level or all (-1)."""
+        _abi.check(_abi.lib().spde_set_tiles(self._hh.h, int(level), int(down), int(up)))
+
+    def get_tiles(self, level: int = 0):
+        d = C.c_int(); u = C.c_int()
+        _abi.check(_abi.lib().spde_get_tiles(self._hh.h, int(level), C.byref(d), C.byref(u)))
+        return d.value, u.value
+
     def timing(self, mode: int):
         _abi.check(_abi.lib().spde_timing(self._hh.h, int(mode)))
 
@@ -250,5 +262,11 @@ class Box:
     def info(self):
         lv = C.c_int(); top = C.c_int(); lds = C.c_int()
         _abi.check(_abi.lib().spde_info(self._hh.h, C.byref(lv), C.byref(top), C.byref(lds)))
+        tiles = []
+        for level in range(lv.value):
+            d = C.c_int(); u = C.c_int()
+            if _abi.lib().spde_get_tiles(self._hh.h, level, C.byref(d), C.byref(u)) != SPDE_OK:
+                break
+            tiles.append((d.value, u.value))
         return {"levels": lv.value, "persistent_top_n": top.value, "device_lds_bytes": lds.value,
-                "workspace_bytes": self._ws.numel()}
+                "workspace_bytes": self._ws.numel(), "tiles": tiles}

@@ -38,6 +38,9 @@ SIGNATURES = {
     "spde_apply_transfer": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "spde_set_graphs": (C.c_int, [_vp, C.c_int]),
     "spde_set_poll_interval": (C.c_int, [_vp, C.c_int]),
+    "spde_set_autotune": (C.c_int, [_vp, C.c_int]),
+    "spde_get_tiles": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "spde_set_tiles": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int]),
     "spde_timing": (C.c_int, [_vp, C.c_int]),
     "spde_kernel_count": (C.c_int, []),
     "spde_kernel_name": (C.c_char_p, [C.c_int]),

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -107,6 +108,7 @@ struct Ctx {
   int poll = 8;
   std::map<int, hipGraphExec_t> graphs;   // batch -> K-iteration graph
   bool tuned = false;
+  bool autotune = true;
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -366,6 +368,139 @@ void close_timing(Ctx* c, int batch) {
   c->ev_used = 0;
 }
 
+// ---- autotuner -----------------------------------------------------------------
+//
+// Chooses the tile shape of every per-level multigrid kernel by timing each
+// admissible shape at the context's largest batch.  The choice is keyed by
+// (device architecture, n, precision) only -- not by batch -- so that every
+// batch size of a context uses the same tiles, and the per-block partial sums
+// (hence the results) do not depend on how many samples share a launch.
+// Choices are kept for the process and, if SPDE_TUNE_CACHE names a file,
+// appended there as lines "key level down up".
+
+std::map<std::string, std::vector<std::pair<int, int>>>& tune_table() {
+  static std::map<std::string, std::vector<std::pair<int, int>>> t;
+  return t;
+}
+
+std::string tune_key(Ctx* c) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
+  const size_t cut = arch.find(':');
+  if (cut != std::string::npos) arch = arch.substr(0, cut);
+  char buf[128];
+  snprintf(buf, sizeof buf, "%s:n%d:%s", arch.c_str(), c->n, c->fp64() ? "fp64" : "mixed");
+  return buf;
+}
+
+void load_tune_file(const std::string& key) {
+  const char* path = getenv("SPDE_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char k[128];
+  int l, d, u;
+  std::vector<std::pair<int, int>> v;
+  while (fscanf(f, "%127s %d %d %d", k, &l, &d, &u) == 4) {
+    if (key != k || l < 0 || l >= kMaxLevels) continue;
+    if ((int)v.size() <= l) v.resize(l + 1, {-1, -1});
+    v[l] = {d, u};
+  }
+  fclose(f);
+  if (!v.empty()) tune_table()[key] = v;
+}
+
+void save_tune_file(const std::string& key, const std::vector<std::pair<int, int>>& v) {
+  const char* path = getenv("SPDE_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  for (size_t l = 0; l < v.size(); ++l) fprintf(f, "%s %zu %d %d\n", key.c_str(), l, v[l].first, v[l].second);
+  fclose(f);
+}
+
+spde_status time_launches(Ctx* c, hipStream_t st, const std::function<hipError_t()>& fn, float* ms) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  hipError_t err = fn();
+  if (err == hipSuccess) err = hipEventRecord(e0, st);
+  for (int k = 0; k < 3 && err == hipSuccess; ++k) err = fn();
+  if (err == hipSuccess) err = hipEventRecord(e1, st);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  if (err == hipSuccess) err = hipEventElapsedTime(ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(SPDE_EHIP, "autotune: %s", hipGetErrorString(err));
+  *ms /= 3.0f;
+  return SPDE_OK;
+}
+
+spde_status autotune(Ctx* c, hipStream_t st) {
+  if (c->tuned) return SPDE_OK;
+  const std::string key = tune_key(c);
+  auto& tab = tune_table();
+  if (!tab.count(key)) load_tune_file(key);
+  const bool f64 = c->fp64();
+  auto it = tab.find(key);
+  bool complete = it != tab.end() && (int)it->second.size() >= c->top;
+  if (complete)
+    for (int l = 0; l < c->top; ++l)
+      if (!shape_ok_down(it->second[l].first, f64) || !shape_ok_up(it->second[l].second, f64)) complete = false;
+  if (!complete && c->autotune) {
+    const int B = c->max_batch;
+    const int64_t nc = c->box.nc;
+    // defined contents for the timing launches
+    HIPCHK(hipMemsetAsync(c->F.vu[0], 0, (size_t)B * nc * 8, st));
+    HIPCHK(hipMemsetAsync(c->F.vs[0], 0, (size_t)B * 3 * nc * 8, st));
+    for (int l = 1; l <= c->top && l < c->nlev; ++l) {
+      HIPCHK(hipMemsetAsync(c->mgb[l], 0, (size_t)B * c->lv[l].nc * c->szm(), st));
+      HIPCHK(hipMemsetAsync(c->mge[l], 0, (size_t)B * c->lv[l].nc * c->szm(), st));
+    }
+    std::vector<std::pair<int, int>> v(c->top, {0, f64 ? 1 : 0});
+    for (int l = 0; l < c->top; ++l) {
+      const bool fine = l == 0;
+      const void* bsrc = fine ? (const void*)c->F.vu[0] : c->mgb[l];
+      void* osrc = fine ? c->F.z[0] : c->mge[l];
+      float best = 1e30f;
+      for (int sh = 0; sh < kNumShapes; ++sh) {
+        if (!shape_ok_down(sh, f64)) continue;
+        float ms = 0.f;
+        spde_status s = time_launches(c, st, [&] {
+          return launch_mg_down(f64, sh, fine, bsrc, bsrc, c->mgb[l + 1], c->lv[l], B, nullptr, st);
+        }, &ms);
+        if (s != SPDE_OK) return s;
+        if (ms < best) { best = ms; v[l].first = sh; }
+      }
+      best = 1e30f;
+      for (int sh = 0; sh < kNumShapes; ++sh) {
+        if (!shape_ok_up(sh, f64)) continue;
+        float ms = 0.f;
+        spde_status s = time_launches(c, st, [&] {
+          return launch_mg_up(f64, sh, fine, bsrc, bsrc, c->mge[l + 1], osrc, osrc, c->lv[l], B, nullptr,
+                              c->F.vs[0], c->F.vs[0], fine ? c->F.part_up : nullptr, c->box, st);
+        }, &ms);
+        if (s != SPDE_OK) return s;
+        if (ms < best) { best = ms; v[l].second = sh; }
+      }
+    }
+    tab[key] = v;
+    save_tune_file(key, v);
+    it = tab.find(key);
+    complete = true;
+  }
+  if (complete) {
+    for (int l = 0; l < c->top; ++l) {
+      c->shape_down[l] = it->second[l].first;
+      c->shape_up[l] = it->second[l].second;
+    }
+  }
+  c->tuned = true;
+  drop_graphs(c);
+  return SPDE_OK;
+}
+
 }  // namespace
 
 // =============================================================================
@@ -506,6 +641,8 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* 
   hipStream_t st = pick_stream(c, stream);
   const Box& bx = c->box;
   const double scale = -c->g * std::pow(bx.h, 1.5);
+  s = autotune(c, st);
+  if (s != SPDE_OK) return s;
   {
     Timed t(c, KID_INIT, 0, st);
     HIPCHK(launch_init(c->F, bx, xi_dev, scale, batch, c->rtol, c->max_iter, st));
@@ -611,6 +748,8 @@ spde_status spde_apply_vcycle(spde_handle h, int batch, const double* r_dev, dou
   HIPCHK(hipSetDevice(c->device));
   hipStream_t st = pick_stream(c, stream);
   void* out = c->fp64() ? (void*)z_dev : c->F.z[0];
+  s = autotune(c, st);
+  if (s != SPDE_OK) return s;
   s = enqueue_vcycle(c, batch, st, 0, r_dev, r_dev, out, out, nullptr, nullptr);
   if (s != SPDE_OK) return s;
   if (!c->fp64()) HIPCHK(launch_f32_to_f64((const float*)c->F.z[0], z_dev, (int64_t)batch * c->box.nc, st));
@@ -632,6 +771,43 @@ spde_status spde_set_graphs(spde_handle h, int enable) {
   Ctx* c = reinterpret_cast<Ctx*>(h);
   if (!c) return fail(SPDE_EINVAL, "null handle");
   c->use_graphs = enable != 0;
+  return SPDE_OK;
+}
+
+spde_status spde_set_autotune(spde_handle h, int enable) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  c->autotune = enable != 0;
+  c->tuned = false;
+  if (c->configured) plan_hierarchy(c);
+  drop_graphs(c);
+  return SPDE_OK;
+}
+
+spde_status spde_set_tiles(spde_handle h, int level, int down_shape, int up_shape) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c || !c->configured) return fail(SPDE_EINVAL, "handle not configured");
+  if (level < -1 || level >= c->top) return fail(SPDE_EINVAL, "level %d has no per-level kernels", level);
+  if (!shape_ok_down(down_shape, c->fp64()) || !shape_ok_up(up_shape, c->fp64()))
+    return fail(SPDE_EINVAL, "tile shape not available for this precision");
+  for (int l = 0; l < c->top; ++l) {
+    if (level == -1 || level == l) {
+      c->shape_down[l] = down_shape;
+      c->shape_up[l] = up_shape;
+    }
+  }
+  c->autotune = false;
+  c->tuned = true;
+  drop_graphs(c);
+  return SPDE_OK;
+}
+
+spde_status spde_get_tiles(spde_handle h, int level, int* down_shape, int* up_shape) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c || !c->configured) return fail(SPDE_EINVAL, "handle not configured");
+  if (level < 0 || level >= c->top) return fail(SPDE_EINVAL, "level %d has no per-level kernels", level);
+  if (down_shape) *down_shape = c->shape_down[level];
+  if (up_shape) *up_shape = c->shape_up[level];
   return SPDE_OK;
 }
 

@@ -53,6 +53,18 @@ __device__ __forceinline__ int nnbr(int x, int y, int z, int m) {
   return (x > 0) + (x < m - 1) + (y > 0) + (y < m - 1) + (z > 0) + (z < m - 1);
 }
 
+// Diagonal d = k2 + a * (number of neighbours) of S~ and its reciprocal.  Only
+// cells on the box boundary have fewer than 6 neighbours; interior cells take
+// the precomputed reciprocal, boundary cells divide.
+template <typename TM>
+struct Diag {
+  TM k2, a, d6, id6;
+  __device__ __forceinline__ Diag(double k2_, double a_)
+      : k2((TM)k2_), a((TM)a_), d6((TM)(k2_ + 6.0 * a_)), id6((TM)(1.0 / (k2_ + 6.0 * a_))) {}
+  __device__ __forceinline__ TM d(int nn) const { return nn == 6 ? d6 : k2 + a * (TM)nn; }
+  __device__ __forceinline__ TM inv(int nn) const { return nn == 6 ? id6 : (TM)1 / (k2 + a * (TM)nn); }
+};
+
 // ---------------------------------------------------------------------------
 // initialisation: v_1 = F = [0; scale * xi], state reset
 
@@ -83,6 +95,46 @@ __global__ __launch_bounds__(kBlock) void k_init(Fields F, Box bx, const double*
 //   x = cA bhat + (cB / d) sum_nbr bhat,
 // and the restricted residual is r_H[I] = sum over the 8 children of
 //   d (bhat - x) + a sum_nbr x.
+// Every phase runs as a compile-time-unrolled batch per thread: all global
+// loads of the batch are issued before any is consumed.
+
+template <int BX, int BY>
+__device__ __forceinline__ void split3(int e, int& lx, int& ly, int& lz) {
+  lx = e % BX;
+  ly = (e / BX) % BY;
+  lz = e / (BX * BY);
+}
+
+__device__ __forceinline__ bool inside(int x, int y, int z, int m) {
+  return (unsigned)x < (unsigned)m && (unsigned)y < (unsigned)m && (unsigned)z < (unsigned)m;
+}
+
+// Load b on the tile grown by H cells (zero outside the box) as bhat = b / d.
+template <typename TM, typename TB, int BX, int BY, int BZ, int H>
+__device__ __forceinline__ void load_bhat(TM* sb, const TB* __restrict__ b, int x0, int y0, int z0, int m,
+                                          const Diag<TM>& D) {
+  constexpr int N = BX * BY * BZ, R = (N + kBlock - 1) / kBlock;
+  TB v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = threadIdx.x + r * kBlock;
+    int lx, ly, lz;
+    split3<BX, BY>(e, lx, ly, lz);
+    const int gx = x0 + lx - H, gy = y0 + ly - H, gz = z0 + lz - H;
+    v[r] = 0;
+    if (e < N && inside(gx, gy, gz, m)) v[r] = b[gx + (int64_t)m * (gy + (int64_t)m * gz)];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = threadIdx.x + r * kBlock;
+    if (e < N) {
+      int lx, ly, lz;
+      split3<BX, BY>(e, lx, ly, lz);
+      const int gx = x0 + lx - H, gy = y0 + ly - H, gz = z0 + lz - H;
+      sb[e] = inside(gx, gy, gz, m) ? (TM)v[r] * D.inv(nnbr(gx, gy, gz, m)) : (TM)0;
+    }
+  }
+}
 
 template <typename TM, typename TB, int TX, int TY, int TZ, bool FINE>
 __global__ __launch_bounds__(kBlock) void k_mg_down(const TB* __restrict__ b0, const TB* __restrict__ b1,
@@ -103,37 +155,40 @@ __global__ __launch_bounds__(kBlock) void k_mg_down(const TB* __restrict__ b0, c
   }
   b += (int64_t)slot * L.nc;
   const int x0 = (t % tpx) * TX, y0 = ((t / tpx) % tpy) * TY, z0 = (t / (tpx * tpy)) * TZ;
-  const TM k2 = (TM)L.k2, a = (TM)L.a, cA = (TM)L.cA, cB = (TM)L.cB;
+  const Diag<TM> D(L.k2, L.a);
+  const TM a = D.a, cA = (TM)L.cA, cB = (TM)L.cB;
 
-  for (int e = threadIdx.x; e < BX * BY * BZ; e += kBlock) {
-    const int lx = e % BX, ly = (e / BX) % BY, lz = e / (BX * BY);
-    const int gx = x0 + lx - 2, gy = y0 + ly - 2, gz = z0 + lz - 2;
-    TM v = 0;
-    if (gx >= 0 && gx < m && gy >= 0 && gy < m && gz >= 0 && gz < m) {
-      const TM d = k2 + a * (TM)nnbr(gx, gy, gz, m);
-      v = (TM)b[gx + (int64_t)m * (gy + (int64_t)m * gz)] / d;
-    }
-    sb[e] = v;
-  }
+  load_bhat<TM, TB, BX, BY, BZ, 2>(sb, b, x0, y0, z0, m, D);
   __syncthreads();
-  for (int e = threadIdx.x; e < XX * XY * XZ; e += kBlock) {
-    const int lx = e % XX, ly = (e / XX) % XY, lz = e / (XX * XY);
-    const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
-    TM v = 0;
-    if (gx >= 0 && gx < m && gy >= 0 && gy < m && gz >= 0 && gz < m) {
-      const int s = (lx + 1) + BX * ((ly + 1) + BY * (lz + 1));
-      const TM sum = sb[s - 1] + sb[s + 1] + sb[s - BX] + sb[s + BX] + sb[s - BX * BY] + sb[s + BX * BY];
-      const TM d = k2 + a * (TM)nnbr(gx, gy, gz, m);
-      v = cA * sb[s] + (cB / d) * sum;
+  {
+    constexpr int N = XX * XY * XZ, R = (N + kBlock - 1) / kBlock;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int e = threadIdx.x + r * kBlock;
+      if (e >= N) break;
+      int lx, ly, lz;
+      split3<XX, XY>(e, lx, ly, lz);
+      const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
+      TM v = 0;
+      if (inside(gx, gy, gz, m)) {
+        const int s = (lx + 1) + BX * ((ly + 1) + BY * (lz + 1));
+        const TM sum = sb[s - 1] + sb[s + 1] + sb[s - BX] + sb[s + BX] + sb[s - BX * BY] + sb[s + BX * BY];
+        v = cA * sb[s] + cB * D.inv(nnbr(gx, gy, gz, m)) * sum;
+      }
+      sx[e] = v;
     }
-    sx[e] = v;
   }
   __syncthreads();
   constexpr int CX = TX / 2, CY = TY / 2, CZ = TZ / 2;
+  constexpr int NC = CX * CY * CZ, RC = (NC + kBlock - 1) / kBlock;
   const int mH = m >> 1;
   TM* r = rH + (int64_t)slot * mH * mH * mH;
-  for (int e = threadIdx.x; e < CX * CY * CZ; e += kBlock) {
-    const int cx = e % CX, cy = (e / CX) % CY, cz = e / (CX * CY);
+#pragma unroll
+  for (int q = 0; q < RC; ++q) {
+    const int e = threadIdx.x + q * kBlock;
+    if (e >= NC) break;
+    int cx, cy, cz;
+    split3<CX, CY>(e, cx, cy, cz);
     const int gcx = (x0 >> 1) + cx, gcy = (y0 >> 1) + cy, gcz = (z0 >> 1) + cz;
     if (gcx >= mH || gcy >= mH || gcz >= mH) continue;
     TM acc = 0;
@@ -142,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_down(const TB* __restrict__ b0, c
       const int lx = 2 * cx + (ch & 1), ly = 2 * cy + ((ch >> 1) & 1), lz = 2 * cz + (ch >> 2);
       const int s = (lx + 2) + BX * ((ly + 2) + BY * (lz + 2));
       const int u = (lx + 1) + XX * ((ly + 1) + XY * (lz + 1));
-      const TM d = k2 + a * (TM)nnbr(x0 + lx, y0 + ly, z0 + lz, m);
+      const TM d = D.d(nnbr(x0 + lx, y0 + ly, z0 + lz, m));
       const TM sum = sx[u - 1] + sx[u + 1] + sx[u - XX] + sx[u + XX] + sx[u - XX * XY] + sx[u + XX * XY];
       acc += d * (sb[s] - sx[u]) + a * sum;
     }
@@ -192,62 +247,85 @@ __global__ __launch_bounds__(kBlock) void k_mg_up(const TB* __restrict__ b0, con
   const int mH = m >> 1;
   const TM* e = eH + (int64_t)slot * mH * mH * mH;
   const int x0 = (t % tpx) * TX, y0 = ((t / tpx) % tpy) * TY, z0 = (t / (tpx * tpy)) * TZ;
-  const TM k2 = (TM)L.k2, a = (TM)L.a, cA = (TM)L.cA, cB = (TM)L.cB;
+  const Diag<TM> D(L.k2, L.a);
+  const TM a = D.a, cA = (TM)L.cA, cB = (TM)L.cB;
   const TM c0 = (TM)L.c0, c1 = (TM)L.c1, c2 = (TM)L.c2;
 
-  for (int i = threadIdx.x; i < BX * BY * BZ; i += kBlock) {
-    const int lx = i % BX, ly = (i / BX) % BY, lz = i / (BX * BY);
-    const int gx = x0 + lx - 3, gy = y0 + ly - 3, gz = z0 + lz - 3;
-    TM v = 0;
-    if (gx >= 0 && gx < m && gy >= 0 && gy < m && gz >= 0 && gz < m) {
-      const TM d = k2 + a * (TM)nnbr(gx, gy, gz, m);
-      v = (TM)b[gx + (int64_t)m * (gy + (int64_t)m * gz)] / d;
+  load_bhat<TM, TB, BX, BY, BZ, 3>(sb, b, x0, y0, z0, m, D);
+  {
+    // coarse corrections of the tile+2 region, loaded while bhat lands in LDS
+    constexpr int N = XX * XY * XZ, R = (N + kBlock - 1) / kBlock;
+    TM ev[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = threadIdx.x + r * kBlock;
+      int lx, ly, lz;
+      split3<XX, XY>(i, lx, ly, lz);
+      const int gx = x0 + lx - 2, gy = y0 + ly - 2, gz = z0 + lz - 2;
+      ev[r] = 0;
+      if (i < N && inside(gx, gy, gz, m))
+        ev[r] = e[(gx >> 1) + (int64_t)mH * ((gy >> 1) + (int64_t)mH * (gz >> 1))];
     }
-    sb[i] = v;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = threadIdx.x + r * kBlock;
+      if (i >= N) break;
+      int lx, ly, lz;
+      split3<XX, XY>(i, lx, ly, lz);
+      const int gx = x0 + lx - 2, gy = y0 + ly - 2, gz = z0 + lz - 2;
+      TM v = 0;
+      if (inside(gx, gy, gz, m)) {
+        const int s = (lx + 1) + BX * ((ly + 1) + BY * (lz + 1));
+        const TM sum = sb[s - 1] + sb[s + 1] + sb[s - BX] + sb[s + BX] + sb[s - BX * BY] + sb[s + BX * BY];
+        v = cA * sb[s] + cB * D.inv(nnbr(gx, gy, gz, m)) * sum + ev[r];
+      }
+      sx[i] = v;
+    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < XX * XY * XZ; i += kBlock) {
-    const int lx = i % XX, ly = (i / XX) % XY, lz = i / (XX * XY);
-    const int gx = x0 + lx - 2, gy = y0 + ly - 2, gz = z0 + lz - 2;
-    TM v = 0;
-    if (gx >= 0 && gx < m && gy >= 0 && gy < m && gz >= 0 && gz < m) {
-      const int s = (lx + 1) + BX * ((ly + 1) + BY * (lz + 1));
-      const TM sum = sb[s - 1] + sb[s + 1] + sb[s - BX] + sb[s + BX] + sb[s - BX * BY] + sb[s + BX * BY];
-      const TM d = k2 + a * (TM)nnbr(gx, gy, gz, m);
-      v = cA * sb[s] + (cB / d) * sum + e[(gx >> 1) + (int64_t)mH * ((gy >> 1) + (int64_t)mH * (gz >> 1))];
+  {
+    constexpr int N = YX * YY * YZ, R = (N + kBlock - 1) / kBlock;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = threadIdx.x + r * kBlock;
+      if (i >= N) break;
+      int lx, ly, lz;
+      split3<YX, YY>(i, lx, ly, lz);
+      const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
+      TM v = 0;
+      if (inside(gx, gy, gz, m)) {
+        const int s = (lx + 2) + BX * ((ly + 2) + BY * (lz + 2));
+        const int u = (lx + 1) + XX * ((ly + 1) + XY * (lz + 1));
+        const TM sum = sx[u - 1] + sx[u + 1] + sx[u - XX] + sx[u + XX] + sx[u - XX * XY] + sx[u + XX * XY];
+        const int nn = nnbr(gx, gy, gz, m);
+        const TM rr = D.d(nn) * (sb[s] - sx[u]) + a * sum;
+        v = c0 * D.inv(nn) * rr;
+      }
+      sy[i] = v;
     }
-    sx[i] = v;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < YX * YY * YZ; i += kBlock) {
-    const int lx = i % YX, ly = (i / YX) % YY, lz = i / (YX * YY);
-    const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
-    TM v = 0;
-    if (gx >= 0 && gx < m && gy >= 0 && gy < m && gz >= 0 && gz < m) {
-      const int s = (lx + 2) + BX * ((ly + 2) + BY * (lz + 2));
-      const int u = (lx + 1) + XX * ((ly + 1) + XY * (lz + 1));
-      const TM sum = sx[u - 1] + sx[u + 1] + sx[u - XX] + sx[u + XX] + sx[u - XX * XY] + sx[u + XX * XY];
-      const TM d = k2 + a * (TM)nnbr(gx, gy, gz, m);
-      const TM r = d * (sb[s] - sx[u]) + a * sum;
-      v = c0 * r / d;
-    }
-    sy[i] = v;
-  }
-  __syncthreads();
+  constexpr int NT = TX * TY * TZ, RT = (NT + kBlock - 1) / kBlock;
   double p_zv = 0.0, p_azz = 0.0;
-  for (int i = threadIdx.x; i < TX * TY * TZ; i += kBlock) {
-    const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int i = threadIdx.x + r * kBlock;
+    if (i >= NT) break;
+    int lx, ly, lz;
+    split3<TX, TY>(i, lx, ly, lz);
     const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-    if (gx >= m || gy >= m || gz >= m) continue;
+    if (!inside(gx, gy, gz, m)) continue;
     const int s = (lx + 3) + BX * ((ly + 3) + BY * (lz + 3));
     const int u = (lx + 2) + XX * ((ly + 2) + XY * (lz + 2));
     const int w = (lx + 1) + YX * ((ly + 1) + YY * (lz + 1));
-    const TM d = k2 + a * (TM)nnbr(gx, gy, gz, m);
+    const int nn = nnbr(gx, gy, gz, m);
+    const TM d = D.d(nn);
     const TM sxn = sx[u - 1] + sx[u + 1] + sx[u - XX] + sx[u + XX] + sx[u - XX * XY] + sx[u + XX * XY];
     const TM syn = sy[w - 1] + sy[w + 1] + sy[w - YX] + sy[w + YX] + sy[w - YX * YY] + sy[w + YX * YY];
-    const TM r = d * (sb[s] - sx[u]) + a * sxn;
-    const TM t2 = r - (d * sy[w] - a * syn);
-    const TM out = sx[u] + c1 * sy[w] + (c2 / d) * t2;
+    const TM rr = d * (sb[s] - sx[u]) + a * sxn;
+    const TM t2 = rr - (d * sy[w] - a * syn);
+    const TM out = sx[u] + c1 * sy[w] + c2 * D.inv(nn) * t2;
     const int64_t g = gx + (int64_t)m * (gy + (int64_t)m * gz);
     const TO zo = (TO)out;
     o[g] = zo;
@@ -266,6 +344,344 @@ __global__ __launch_bounds__(kBlock) void k_mg_up(const TB* __restrict__ b0, con
       p_zv += z * (double)b[g];
       p_azz += bxc.q * fq + 2.0 * z * bxc.h2q * dv - bxc.k2h3 * z * z;
     }
+  }
+  if (FINE && part) {
+    p_zv = block_sum(p_zv, red);
+    p_azz = block_sum(p_azz, red);
+    if (threadIdx.x == 0) {
+      part[((int64_t)slot * nb + t) * 2 + 0] = p_zv;
+      part[((int64_t)slot * nb + t) * 2 + 1] = p_azz;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// multigrid level kernels, 2.5-D variant: a block owns a TX x TY column tile
+// (one column per thread) and marches through ZC planes in z, keeping the
+// planes a stencil step needs in LDS rings.  The next plane's global loads are
+// issued into registers before the current plane is processed.  Same
+// arithmetic as the 3-D tile kernels above, element for element.
+
+template <int TX, int TY, int H>
+struct Plane {
+  static constexpr int W = TX + 2 * H, HH = TY + 2 * H, A = W * HH, R = (A + kBlock - 1) / kBlock;
+};
+
+template <typename TM, typename TB, int TX, int TY, int ZC, bool FINE>
+__global__ __launch_bounds__(kBlock) void k_mg_down_zs(const TB* __restrict__ b0, const TB* __restrict__ b1,
+                                                       TM* __restrict__ rH, Level L, int nb,
+                                                       const Scalars* __restrict__ sc) {
+  static_assert(TX * TY == kBlock && TX <= 32 && (TX % 2) == 0 && (TY % 2) == 0 && (ZC % 2) == 0, "tile");
+  using PB = Plane<TX, TY, 2>;
+  using PX = Plane<TX, TY, 1>;
+  __shared__ TM sb[3][PB::A];
+  __shared__ TM sx[3][PX::A];
+  const int m = L.m;
+  const int64_t m2 = (int64_t)m * m;
+  const int tpx = (m + TX - 1) / TX, tpy = (m + TY - 1) / TY;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int slot = lb / nb, t = lb - slot * nb;
+  const TB* b = b0;
+  if (sc) {
+    if (sc[slot].state != ST_ACTIVE) return;
+    if (FINE && (sc[slot].it & 1)) b = b1;
+  }
+  b += (int64_t)slot * L.nc;
+  const int x0 = (t % tpx) * TX, y0 = ((t / tpx) % tpy) * TY, z0 = (t / (tpx * tpy)) * ZC;
+  const int z1 = min(z0 + ZC, m);
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int gx = x0 + tx, gy = y0 + ty;
+  const bool own = gx < m && gy < m;
+  const Diag<TM> D(L.k2, L.a);
+  const TM a = D.a, cA = (TM)L.cA, cB = (TM)L.cB;
+
+  int boff[PB::R], bnn[PB::R];
+  bool bok[PB::R];
+#pragma unroll
+  for (int k = 0; k < PB::R; ++k) {
+    const int p = threadIdx.x + k * kBlock;
+    const int hx = x0 + p % PB::W - 2, hy = y0 + p / PB::W - 2;
+    bok[k] = p < PB::A && (unsigned)hx < (unsigned)m && (unsigned)hy < (unsigned)m;
+    boff[k] = bok[k] ? hx + m * hy : 0;
+    bnn[k] = (hx > 0) + (hx < m - 1) + (hy > 0) + (hy < m - 1);
+  }
+  TB pf[PB::R];
+  auto fetch = [&](int z) {
+    const bool zin = (unsigned)z < (unsigned)m;
+#pragma unroll
+    for (int k = 0; k < PB::R; ++k) pf[k] = (bok[k] && zin) ? b[boff[k] + m2 * z] : (TB)0;
+  };
+  const int zb = z0 - 2;
+  fetch(zb);
+  TM acc = 0;
+  const int nnxy = (gx > 0) + (gx < m - 1) + (gy > 0) + (gy < m - 1);
+  const int mH = m >> 1;
+  TM* r_out = rH + (int64_t)slot * mH * mH * mH;
+  for (int s = zb; s <= z1 + 1; ++s) {
+    {
+      TM* bs = sb[(s - zb) % 3];
+      const int zn = (s > 0) + (s < m - 1);
+#pragma unroll
+      for (int k = 0; k < PB::R; ++k) {
+        const int p = threadIdx.x + k * kBlock;
+        if (p < PB::A) bs[p] = (TM)pf[k] * D.inv(bnn[k] + zn);
+      }
+    }
+    if (s + 1 <= z1 + 1) fetch(s + 1);
+    __syncthreads();
+    const int zx = s - 1;
+    if (zx >= z0 - 1) {
+      TM* xs = sx[(zx - (z0 - 1)) % 3];
+      const TM* bm = sb[(zx - 1 - zb) % 3];
+      const TM* bc = sb[(zx - zb) % 3];
+      const TM* bp = sb[(zx + 1 - zb) % 3];
+      const bool zin = (unsigned)zx < (unsigned)m;
+      const int zn = (zx > 0) + (zx < m - 1);
+#pragma unroll
+      for (int k = 0; k < PX::R; ++k) {
+        const int p = threadIdx.x + k * kBlock;
+        if (p < PX::A) {
+          const int lx = p % PX::W, ly = p / PX::W;
+          const int hx = x0 + lx - 1, hy = y0 + ly - 1;
+          TM v = 0;
+          if (zin && (unsigned)hx < (unsigned)m && (unsigned)hy < (unsigned)m) {
+            const int q = (lx + 1) + PB::W * (ly + 1);
+            const TM sum = bc[q - 1] + bc[q + 1] + bc[q - PB::W] + bc[q + PB::W] + bm[q] + bp[q];
+            const int nn = (hx > 0) + (hx < m - 1) + (hy > 0) + (hy < m - 1) + zn;
+            v = cA * bc[q] + cB * D.inv(nn) * sum;
+          }
+          xs[p] = v;
+        }
+      }
+    }
+    __syncthreads();
+    const int zr = s - 2;
+    if (zr >= z0 && zr < z1) {
+      TM r = 0;
+      if (own) {
+        const int q = (tx + 2) + PB::W * (ty + 2);
+        const int u = (tx + 1) + PX::W * (ty + 1);
+        const TM* xc = sx[(zr - (z0 - 1)) % 3];
+        const TM* xm = sx[(zr - 1 - (z0 - 1)) % 3];
+        const TM* xp = sx[(zr + 1 - (z0 - 1)) % 3];
+        const TM d = D.d(nnxy + (zr > 0) + (zr < m - 1));
+        const TM sum = xc[u - 1] + xc[u + 1] + xc[u - PX::W] + xc[u + PX::W] + xm[u] + xp[u];
+        r = d * (sb[(zr - zb) % 3][q] - xc[u]) + a * sum;
+      }
+      acc += r;
+      if (zr & 1) {
+        TM v = acc + __shfl_xor(acc, 1, 64);
+        v += __shfl_xor(v, TX, 64);
+        if (own && !(tx & 1) && !(ty & 1))
+          r_out[(gx >> 1) + (int64_t)mH * ((gy >> 1) + (int64_t)mH * (zr >> 1))] = v;
+        acc = 0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename TM, typename TB, typename TO, int TX, int TY, int ZC, bool FINE>
+__global__ __launch_bounds__(kBlock) void k_mg_up_zs(const TB* __restrict__ b0, const TB* __restrict__ b1,
+                                                     const TM* __restrict__ eH, TO* __restrict__ o0,
+                                                     TO* __restrict__ o1, Level L, int nb,
+                                                     const Scalars* __restrict__ sc,
+                                                     const double* __restrict__ vs0,
+                                                     const double* __restrict__ vs1,
+                                                     double* __restrict__ part, Box bxc) {
+  static_assert(TX * TY == kBlock && (TX % 2) == 0 && (TY % 2) == 0 && (ZC % 2) == 0, "tile");
+  using PB = Plane<TX, TY, 3>;
+  using PX = Plane<TX, TY, 2>;
+  using PY = Plane<TX, TY, 1>;
+  __shared__ TM sb[4][PB::A];
+  __shared__ TM sx[4][PX::A];
+  __shared__ TM sy[3][PY::A];
+  __shared__ double red[kBlock / 64];
+  const int m = L.m;
+  const int64_t m2 = (int64_t)m * m;
+  const int tpx = (m + TX - 1) / TX, tpy = (m + TY - 1) / TY;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int slot = lb / nb, t = lb - slot * nb;
+  const TB* b = b0;
+  TO* o = o0;
+  const double* vs = vs0;
+  if (sc) {
+    if (sc[slot].state != ST_ACTIVE) return;
+    if (FINE && (sc[slot].it & 1)) { b = b1; o = o1; vs = vs1; }
+  }
+  b += (int64_t)slot * L.nc;
+  o += (int64_t)slot * L.nc;
+  const int mH = m >> 1;
+  const int64_t mH2 = (int64_t)mH * mH;
+  const TM* e = eH + (int64_t)slot * mH2 * mH;
+  const int x0 = (t % tpx) * TX, y0 = ((t / tpx) % tpy) * TY, z0 = (t / (tpx * tpy)) * ZC;
+  const int z1 = min(z0 + ZC, m);
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int gx = x0 + tx, gy = y0 + ty;
+  const bool own = gx < m && gy < m;
+  const Diag<TM> D(L.k2, L.a);
+  const TM a = D.a, cA = (TM)L.cA, cB = (TM)L.cB;
+  const TM c0 = (TM)L.c0, c1 = (TM)L.c1, c2 = (TM)L.c2;
+
+  int boff[PB::R], bnn[PB::R];
+  bool bok[PB::R];
+#pragma unroll
+  for (int k = 0; k < PB::R; ++k) {
+    const int p = threadIdx.x + k * kBlock;
+    const int hx = x0 + p % PB::W - 3, hy = y0 + p / PB::W - 3;
+    bok[k] = p < PB::A && (unsigned)hx < (unsigned)m && (unsigned)hy < (unsigned)m;
+    boff[k] = bok[k] ? hx + m * hy : 0;
+    bnn[k] = (hx > 0) + (hx < m - 1) + (hy > 0) + (hy < m - 1);
+  }
+  int eoff[PX::R];
+  bool eok[PX::R];
+#pragma unroll
+  for (int k = 0; k < PX::R; ++k) {
+    const int p = threadIdx.x + k * kBlock;
+    const int hx = x0 + p % PX::W - 2, hy = y0 + p / PX::W - 2;
+    eok[k] = p < PX::A && (unsigned)hx < (unsigned)m && (unsigned)hy < (unsigned)m;
+    eoff[k] = eok[k] ? (hx >> 1) + mH * (hy >> 1) : 0;
+  }
+  TB pf[PB::R];
+  TM pe[PX::R], pe_next[PX::R];
+  auto fetch_b = [&](int z) {
+    const bool zin = (unsigned)z < (unsigned)m;
+#pragma unroll
+    for (int k = 0; k < PB::R; ++k) pf[k] = (bok[k] && zin) ? b[boff[k] + m2 * z] : (TB)0;
+  };
+  auto fetch_e = [&](TM* dst, int z) {
+    const bool zin = (unsigned)z < (unsigned)m;
+#pragma unroll
+    for (int k = 0; k < PX::R; ++k) dst[k] = (eok[k] && zin) ? e[eoff[k] + mH2 * (z >> 1)] : (TM)0;
+  };
+  // face values for the partial sums of the output plane (fine level only)
+  // (pv: plane output at this step; pvn: plane output at the next step)
+  double pv[7] = {0, 0, 0, 0, 0, 0, 0}, pvn[7] = {0, 0, 0, 0, 0, 0, 0};
+  const int64_t nc = bxc.nc;
+  const double* vx = vs + face_off(slot, 0, nc);
+  const double* vy = vs + face_off(slot, 1, nc);
+  const double* vz = vs + face_off(slot, 2, nc);
+  auto fetch_v = [&](int z) {
+    if (FINE && part && own && (unsigned)z < (unsigned)m) {
+      const int64_t g = gx + (int64_t)m * gy + m2 * z;
+      pvn[0] = vx[g]; pvn[1] = vy[g]; pvn[2] = vz[g];
+      pvn[3] = (gx < m - 1) ? vx[g + 1] : 0.0;
+      pvn[4] = (gy < m - 1) ? vy[g + m] : 0.0;
+      pvn[5] = (z < m - 1) ? vz[g + m2] : 0.0;
+      pvn[6] = (double)b[g];
+    }
+  };
+  const int zb = z0 - 3;
+  const int nnxy = (gx > 0) + (gx < m - 1) + (gy > 0) + (gy < m - 1);
+  double p_zv = 0.0, p_azz = 0.0;
+  fetch_b(zb);
+#pragma unroll
+  for (int k = 0; k < PX::R; ++k) pe[k] = 0;
+  for (int s = zb; s <= z1 + 2; ++s) {
+    {
+      TM* bs = sb[(s - zb) & 3];
+      const int zn = (s > 0) + (s < m - 1);
+#pragma unroll
+      for (int k = 0; k < PB::R; ++k) {
+        const int p = threadIdx.x + k * kBlock;
+        if (p < PB::A) bs[p] = (TM)pf[k] * D.inv(bnn[k] + zn);
+      }
+    }
+    if (s + 1 <= z1 + 2) fetch_b(s + 1);
+    fetch_e(pe_next, s);        // corrections of plane s (used at the next step)
+    fetch_v(s - 2);             // faces of the plane output at the next step
+    __syncthreads();
+    const int zx = s - 1;
+    if (zx >= z0 - 2) {
+      TM* xs = sx[(zx - (z0 - 2)) & 3];
+      const TM* bm = sb[(zx - 1 - zb) & 3];
+      const TM* bc = sb[(zx - zb) & 3];
+      const TM* bp = sb[(zx + 1 - zb) & 3];
+      const bool zin = (unsigned)zx < (unsigned)m;
+      const int zn = (zx > 0) + (zx < m - 1);
+#pragma unroll
+      for (int k = 0; k < PX::R; ++k) {
+        const int p = threadIdx.x + k * kBlock;
+        if (p < PX::A) {
+          const int lx = p % PX::W, ly = p / PX::W;
+          const int hx = x0 + lx - 2, hy = y0 + ly - 2;
+          TM v = 0;
+          if (zin && (unsigned)hx < (unsigned)m && (unsigned)hy < (unsigned)m) {
+            const int q = (lx + 1) + PB::W * (ly + 1);
+            const TM sum = bc[q - 1] + bc[q + 1] + bc[q - PB::W] + bc[q + PB::W] + bm[q] + bp[q];
+            const int nn = (hx > 0) + (hx < m - 1) + (hy > 0) + (hy < m - 1) + zn;
+            v = cA * bc[q] + cB * D.inv(nn) * sum + pe[k];
+          }
+          xs[p] = v;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < PX::R; ++k) pe[k] = pe_next[k];
+    __syncthreads();
+    const int zy = s - 2;
+    if (zy >= z0 - 1) {
+      TM* ys = sy[(zy - (z0 - 1)) % 3];
+      const TM* xm = sx[(zy - 1 - (z0 - 2)) & 3];
+      const TM* xc = sx[(zy - (z0 - 2)) & 3];
+      const TM* xp = sx[(zy + 1 - (z0 - 2)) & 3];
+      const TM* bc = sb[(zy - zb) & 3];
+      const bool zin = (unsigned)zy < (unsigned)m;
+      const int zn = (zy > 0) + (zy < m - 1);
+#pragma unroll
+      for (int k = 0; k < PY::R; ++k) {
+        const int p = threadIdx.x + k * kBlock;
+        if (p < PY::A) {
+          const int lx = p % PY::W, ly = p / PY::W;
+          const int hx = x0 + lx - 1, hy = y0 + ly - 1;
+          TM v = 0;
+          if (zin && (unsigned)hx < (unsigned)m && (unsigned)hy < (unsigned)m) {
+            const int q = (lx + 2) + PB::W * (ly + 2);
+            const int u = (lx + 1) + PX::W * (ly + 1);
+            const TM sum = xc[u - 1] + xc[u + 1] + xc[u - PX::W] + xc[u + PX::W] + xm[u] + xp[u];
+            const int nn = (hx > 0) + (hx < m - 1) + (hy > 0) + (hy < m - 1) + zn;
+            const TM rr = D.d(nn) * (bc[q] - xc[u]) + a * sum;
+            v = c0 * D.inv(nn) * rr;
+          }
+          ys[p] = v;
+        }
+      }
+    }
+    __syncthreads();
+    const int zo = s - 3;
+    if (zo >= z0 && zo < z1 && own) {
+      const int q = (tx + 3) + PB::W * (ty + 3);
+      const int u = (tx + 2) + PX::W * (ty + 2);
+      const int w = (tx + 1) + PY::W * (ty + 1);
+      const TM* xm = sx[(zo - 1 - (z0 - 2)) & 3];
+      const TM* xc = sx[(zo - (z0 - 2)) & 3];
+      const TM* xp = sx[(zo + 1 - (z0 - 2)) & 3];
+      const TM* ym = sy[(zo - 1 - (z0 - 1)) % 3];
+      const TM* yc = sy[(zo - (z0 - 1)) % 3];
+      const TM* yp = sy[(zo + 1 - (z0 - 1)) % 3];
+      const int nn = nnxy + (zo > 0) + (zo < m - 1);
+      const TM d = D.d(nn);
+      const TM sxn = xc[u - 1] + xc[u + 1] + xc[u - PX::W] + xc[u + PX::W] + xm[u] + xp[u];
+      const TM syn = yc[w - 1] + yc[w + 1] + yc[w - PY::W] + yc[w + PY::W] + ym[w] + yp[w];
+      const TM rr = d * (sb[(zo - zb) & 3][q] - xc[u]) + a * sxn;
+      const TM t2 = rr - (d * yc[w] - a * syn);
+      const TM out = xc[u] + c1 * yc[w] + c2 * D.inv(nn) * t2;
+      const int64_t g = gx + (int64_t)m * gy + m2 * zo;
+      const TO zo_v = (TO)out;
+      o[g] = zo_v;
+      if (FINE && part) {
+        const double z = (double)zo_v;
+        const double fq = pv[0] * (pv[0] + 0.5 * pv[3]) + pv[1] * (pv[1] + 0.5 * pv[4]) + pv[2] * (pv[2] + 0.5 * pv[5]);
+        const double dv = (pv[3] - pv[0]) + (pv[4] - pv[1]) + (pv[5] - pv[2]);
+        p_zv += z * pv[6];
+        p_azz += bxc.q * fq + 2.0 * z * bxc.h2q * dv - bxc.k2h3 * z * z;
+      }
+    }
+    if (FINE && part) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) pv[k] = pvn[k];
+    }
+    __syncthreads();
   }
   if (FINE && part) {
     p_zv = block_sum(p_zv, red);

@@ -102,7 +102,8 @@ def test_box64_batch(torch_cuda, prec, bar):
     w = WORKLOADS["box64"]
     say(f"box64 {prec} batch=8")
     xi = w.noise(8)
-    box, out = _run_sample(torch, w.n, w.kappa, prec, xi)
+    box, out = _run_sample(torch, w.n, w.kappa, prec, xi, allow_notconv=True)
+    say(f"box64 {prec}: tiles {box.info()['tiles']} status {out['status']}")
     u = out["u_box"].cpu().numpy()
     u_ref = oracle_u(w.n, w.kappa, w.g, xi)
     errs = [rel_l2(u[b], u_ref[b]) for b in range(xi.shape[0])]
@@ -174,3 +175,46 @@ def test_restrict_noise_matches_oracle(torch_cuda):
     xc = PP.restrict_noise(torch.tensor(xi, device="cuda"), 32).cpu().numpy()
     ref = noise.restrict_batch(32, xi)
     assert np.abs(xc - ref).max() <= 4e-16 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_every_tile_shape_gives_the_same_vcycle(torch_cuda, prec):
+    """All tile shapes compute the same V-cycle up to summation order, and each
+    is symmetric positive definite (MINRES needs an SPD preconditioner)."""
+    torch = torch_cuda
+    n = 32
+    say(f"tile shapes {prec} n={n}")
+    rng = np.random.default_rng(9)
+    r = torch.tensor(rng.standard_normal((2, n ** 3)), device="cuda")
+    box = P().Box(n, 20.0, precision=prec, max_batch=2)
+    box.set_tiles(0, 0 if prec == "mixed" else 1)
+    ref = box.apply_vcycle(r).cpu().numpy()
+    rn = r.cpu().numpy()
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    ok_up = set(range(10)) if prec == "mixed" else {1, 4, 5, 6, 7, 8, 9}
+    pairs = [(d, d if d in ok_up else 6) for d in range(10)]
+    bad = []
+    for d, u in pairs:
+        box.set_tiles(d, u)
+        z = box.apply_vcycle(r).cpu().numpy()
+        err = np.abs(z - ref).max() / np.abs(ref).max()
+        a = float(rn[0] @ z[1]); b = float(rn[1] @ z[0])
+        asym = abs(a - b) / np.sqrt(abs((rn[0] @ z[0]) * (rn[1] @ z[1])))
+        say(f"  shapes down={d} up={u}: max rel diff {err:.3e}, asymmetry {asym:.3e}")
+        if not (err <= tol and asym <= (1e-12 if prec == "fp64" else 1e-5)):
+            bad.append((d, u, err, asym))
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("shape", [1, 6, 7, 9])
+def test_sample_with_tile_shape(torch_cuda, shape):
+    torch = torch_cuda
+    say(f"sample with tile shape {shape} n=64")
+    w = WORKLOADS["box64"]
+    xi = w.noise(2)
+    box = P().Box(w.n, w.kappa, precision="fp64", max_batch=2)
+    box.set_tiles(shape, shape)
+    out = box.sample(torch.tensor(xi, device="cuda"), u_box=True)
+    u = out["u_box"].cpu().numpy()
+    ref = oracle_u(w.n, w.kappa, w.g, xi)
+    assert max(rel_l2(u[b], ref[b]) for b in range(2)) <= 1e-10
