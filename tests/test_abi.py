@@ -1,0 +1,140 @@
+"""CPU checks of the C interface: exported symbols, argument validation, and the
+host-side transfer builder against the oracle (no GPU needed)."""
+import ctypes as C
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import transfer as T
+from workloads import WORKLOADS, tet_mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1712_06758_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        sys.path.insert(0, ROOT)
+        from paper_1712_06758_amd.build import build
+        build()
+    return _abi.lib()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "spde.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(spde_\w+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_1712_06758_amd._abi import SIGNATURES
+    assert sorted(SIGNATURES) == names
+
+
+def setup(lib, n=16, kappa=10.0, g=1.0):
+    h = C.c_void_p()
+    st = lib.spde_setup_box(n, kappa, g, C.byref(h))
+    return st, h
+
+
+def test_setup_validation(lib):
+    for n, kappa, g in [(3, 1.0, 1.0), (6, 1.0, 1.0), (2048, 1.0, 1.0), (16, 0.0, 1.0), (16, -1.0, 1.0),
+                        (16, 1.0, 0.0), (16, float("nan"), 1.0), (16, 1.0, float("inf"))]:
+        st, h = setup(lib, n, kappa, g)
+        assert st == -1, (n, kappa, g)
+        assert not h.value
+        assert lib.spde_last_error()
+    st, h = setup(lib, 16)
+    assert st == 0 and h.value
+    lib.spde_destroy(h)
+
+
+def test_configure_and_workspace(lib):
+    st, h = setup(lib, 32)
+    assert lib.spde_workspace_bytes(h) == 0          # not configured
+    for prec, rtol, it, mb in [(2, 1e-8, 10, 1), (0, 0.0, 10, 1), (0, 1.0, 10, 1), (0, 1e-8, 0, 1),
+                               (0, 1e-8, 10, 0), (0, 1e-8, 10, 5000)]:
+        assert lib.spde_configure(h, prec, rtol, it, mb) == -1
+    assert lib.spde_configure(h, 0, 1e-10, 100, 1) == 0
+    w1 = lib.spde_workspace_bytes(h)
+    assert lib.spde_configure(h, 0, 1e-10, 100, 4) == 0
+    w4 = lib.spde_workspace_bytes(h)
+    assert lib.spde_configure(h, 1, 1e-8, 100, 4) == 0
+    w4m = lib.spde_workspace_bytes(h)
+    nc = 32 ** 3
+    # 13 float64 cell-sized arrays per sample at least (6 face, 7 cell)
+    assert w1 >= 13 * 8 * nc
+    assert 3.5 * w1 < w4 < 4.5 * w1
+    assert w4m < w4                                   # float32 multigrid state
+    # sampling before a workspace is bound fails cleanly (no GPU touched)
+    assert lib.spde_sample(h, 1, C.c_void_p(8), None, None, None, None, None, None) == -1
+    assert lib.spde_restrict_noise(7, 1, C.c_void_p(8), C.c_void_p(8), None) == -1
+    lib.spde_destroy(h)
+
+
+def test_kernel_names(lib):
+    import paper_1712_06758_amd as P
+    names = P.kernel_names()
+    assert "operator" in names and "mg_up_fine" in names and "spmm" in names
+
+
+@pytest.mark.parametrize("name,rows", [("box16", 200), ("box64", 40)])
+def test_host_transfer_matches_oracle(lib, name, rows):
+    """The library's clipper (successive half-space splitting of tets) against
+    the oracle's vertex enumeration + convex hull volumes, on sampled rows."""
+    import paper_1712_06758_amd as P
+    w = WORKLOADS[name]
+    xyz, tets = w.mesh()
+    rp, ci, cv = P.build_transfer_host(w.n, xyz, tets)
+    assert rp.shape == (tets.shape[0] + 1,) and rp[0] == 0 and rp[-1] == ci.size
+    # every row sums to one (the tets lie inside the box) and columns ascend
+    sums = np.add.reduceat(cv, rp[:-1])
+    np.testing.assert_allclose(sums, 1.0, atol=1e-12)
+    sel = np.random.default_rng(1).choice(tets.shape[0], rows, replace=False)
+    for r in sel:
+        c_or, v_or = T.tet_row(xyz, tets[r], w.n)
+        got = dict(zip(ci[rp[r]:rp[r + 1]].tolist(), cv[rp[r]:rp[r + 1]].tolist()))
+        assert np.all(np.diff(ci[rp[r]:rp[r + 1]]) > 0)
+        ref = dict(zip(c_or.tolist(), v_or.tolist()))
+        for k in set(got) | set(ref):
+            assert abs(got.get(k, 0.0) - ref.get(k, 0.0)) <= 1e-12, (r, k)
+
+
+def test_host_transfer_aligned_mesh_is_injection(lib):
+    import paper_1712_06758_amd as P
+    n = 4
+    xyz, tets = tet_mesh(0.0, 1.0, n, jitter=0.0)
+    rp, ci, cv = P.build_transfer_host(n, xyz, tets)
+    assert np.all(np.diff(rp) == 1)
+    np.testing.assert_allclose(cv, 1.0, atol=1e-14)
+
+
+def test_host_transfer_rejects_bad_meshes(lib):
+    import paper_1712_06758_amd as P
+    from paper_1712_06758_amd import SpdeError
+    xyz, tets = tet_mesh(0.2, 0.8, 2)
+    bad = xyz.copy(); bad[3] = (1.2, 0.5, 0.5)
+    with pytest.raises(SpdeError):
+        P.build_transfer_host(8, bad, tets)
+    flat = xyz.copy(); flat[:, 2] = 0.5
+    with pytest.raises(SpdeError):
+        P.build_transfer_host(8, flat, tets)
+    idx = tets.copy(); idx[0, 0] = xyz.shape[0]
+    with pytest.raises(SpdeError):
+        P.build_transfer_host(8, xyz, idx)
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
