@@ -148,6 +148,42 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev,
 spde_status spde_restrict_noise(int n_fine, int batch, const double* xi_f_dev,
                                 double* xi_c_dev, void* stream);
 
+/* ---- continuous batching (serving) ---------------------------------------
+ * The slots [0, max_batch) of a handle are independent MINRES instances on the
+ * same box.  A caller may start a new sample in an idle slot at any time while
+ * other slots iterate; every slot's arithmetic is independent of the others,
+ * so a sample's result is bitwise the same whichever slots share its launches.
+ * Slot states returned by spde_slots_poll:
+ *   0 iterating, 1 converged, 2 stopped at max_iter, 3 failed, 4 idle. */
+
+/* Mark slots [0, nslots) idle.  Call once before using the slot interface. */
+spde_status spde_slots_reset(spde_handle h, int nslots, void* stream);
+
+/* Start a sample in `slot` from the noise xi_dev [n^3] (the slot must be idle
+ * or finished).  Asynchronous on `stream`. */
+spde_status spde_slot_start(spde_handle h, int slot, const double* xi_dev, void* stream);
+
+/* Enqueue `iters` MINRES iterations over slots [0, nslots); idle and finished
+ * slots are skipped on the device.  Asynchronous on `stream`. */
+spde_status spde_slots_step(spde_handle h, int nslots, int iters, void* stream);
+
+/* Blocking: copy the states and iteration counts of slots [0, nslots) to the
+ * host arrays (nullable). */
+spde_status spde_slots_poll(spde_handle h, int nslots, int* state_host, int* iters_host,
+                            void* stream);
+
+/* Write the field of a converged slot to u_box_dev [n^3] (nullable: discard)
+ * and mark the slot idle.  Asynchronous on `stream`. */
+spde_status spde_slot_finish(spde_handle h, int slot, double* u_box_dev, void* stream);
+
+/* Stateless CSR SpMM y[b] = A x[b] for b < batch (the transfer apply with an
+ * explicit matrix, Sec. "L2-Projection", eq. proj_op).  x [batch][n_cols],
+ * y [batch][n_rows]; rows with indices outside [0, n_cols) skip them.
+ * Asynchronous on `stream`. */
+spde_status spde_csr_apply(int64_t n_rows, int64_t nnz, const int64_t* row_ptr_dev,
+                           const int32_t* col_dev, const double* val_dev, int64_t n_cols,
+                           int batch, const double* x_dev, double* y_dev, void* stream);
+
 /* ---- operators exposed for verification -------------------------------- */
 
 /* y = A x with A the saddle-point matrix of eq. linsys_blocks on the full

@@ -46,6 +46,12 @@ SIGNATURES = {
     "spde_kernel_name": (C.c_char_p, [C.c_int]),
     "spde_timing_get": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_double), _i64p, C.POINTER(C.c_double)]),
     "spde_info": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "spde_slots_reset": (C.c_int, [_vp, C.c_int, _vp]),
+    "spde_slot_start": (C.c_int, [_vp, C.c_int, _vp, _vp]),
+    "spde_slots_step": (C.c_int, [_vp, C.c_int, C.c_int, _vp]),
+    "spde_slots_poll": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "spde_slot_finish": (C.c_int, [_vp, C.c_int, _vp, _vp]),
+    "spde_csr_apply": (C.c_int, [C.c_int64, C.c_int64, _vp, _vp, _vp, C.c_int64, C.c_int, _vp, _vp, _vp]),
     "spde_free_host": (None, [_vp]),
     "spde_destroy": (None, [_vp]),
     "spde_last_error": (C.c_char_p, []),

@@ -645,7 +645,7 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* 
   if (s != SPDE_OK) return s;
   {
     Timed t(c, KID_INIT, 0, st);
-    HIPCHK(launch_init(c->F, bx, xi_dev, scale, batch, c->rtol, c->max_iter, st));
+    HIPCHK(launch_init(c->F, bx, xi_dev, scale, batch, c->rtol, c->max_iter, 0, st));
   }
   const bool graphs = c->use_graphs && !c->timing && st != nullptr;
   int launched = 0;
@@ -683,7 +683,7 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* 
     if (sc.state == ST_ACTIVE || (sc.flags & FL_NOTCONV)) notconv = true;
     if (iters_host) iters_host[b] = sc.state == ST_ACTIVE ? launched : sc.iters;
   }
-  HIPCHK(launch_fix_solution(c->F, bx, batch, st));
+  HIPCHK(launch_fix_solution(c->F, bx, batch, 0, st));
   if (u_box_dev) HIPCHK(hipMemcpyAsync(u_box_dev, c->F.x, (size_t)batch * bx.nc * 8, hipMemcpyDeviceToDevice, st));
   if (sigma_dev || relres_host) {
     double* sig_int = relres_host ? c->F.vs[0] : nullptr;
@@ -710,6 +710,111 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* 
   close_timing(c, batch);
   if (failed) return fail(SPDE_EFAILED, "breakdown or non-finite value in some sample");
   if (notconv) return fail(SPDE_ENOTCONV, "max_iter reached for some sample");
+  return SPDE_OK;
+}
+
+// ---- continuous batching ----------------------------------------------------
+
+spde_status spde_slots_reset(spde_handle h, int nslots, void* stream) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  spde_status s = check_ready(c);
+  if (s != SPDE_OK) return s;
+  if (nslots < 1 || nslots > c->max_batch) return fail(SPDE_EINVAL, "nslots out of range");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = pick_stream(c, stream);
+  s = autotune(c, st);
+  if (s != SPDE_OK) return s;
+  HIPCHK(launch_set_state(c->F.sc, 0, nslots, ST_IDLE, st));
+  return SPDE_OK;
+}
+
+spde_status spde_slot_start(spde_handle h, int slot, const double* xi_dev, void* stream) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  spde_status s = check_ready(c);
+  if (s != SPDE_OK) return s;
+  if (slot < 0 || slot >= c->max_batch) return fail(SPDE_EINVAL, "slot out of range");
+  if (!xi_dev) return fail(SPDE_EINVAL, "xi is null");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = pick_stream(c, stream);
+  const double scale = -c->g * std::pow(c->box.h, 1.5);
+  HIPCHK(launch_init(c->F, c->box, xi_dev, scale, 1, c->rtol, c->max_iter, slot, st));
+  return SPDE_OK;
+}
+
+spde_status spde_slots_step(spde_handle h, int nslots, int iters, void* stream) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  spde_status s = check_ready(c);
+  if (s != SPDE_OK) return s;
+  if (nslots < 1 || nslots > c->max_batch) return fail(SPDE_EINVAL, "nslots out of range");
+  if (iters < 1) return fail(SPDE_EINVAL, "iters must be >= 1");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = pick_stream(c, stream);
+  const bool graphs = c->use_graphs && !c->timing && st != nullptr;
+  int done = 0;
+  while (done < iters) {
+    hipGraphExec_t ex = nullptr;
+    if (graphs && iters - done >= c->poll && get_graph(c, nslots, st, &ex) != SPDE_OK) {
+      hipGetLastError();
+      c->use_graphs = false;
+      ex = nullptr;
+    }
+    if (ex) {
+      HIPCHK(hipGraphLaunch(ex, st));
+      done += c->poll;
+    } else {
+      s = enqueue_iteration(c, nslots, st, 0);
+      if (s != SPDE_OK) return s;
+      done += 1;
+    }
+  }
+  return SPDE_OK;
+}
+
+spde_status spde_slots_poll(spde_handle h, int nslots, int* state_host, int* iters_host, void* stream) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  spde_status s = check_ready(c);
+  if (s != SPDE_OK) return s;
+  if (nslots < 1 || nslots > c->max_batch) return fail(SPDE_EINVAL, "nslots out of range");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = pick_stream(c, stream);
+  HIPCHK(hipMemcpyAsync(c->host_sc, c->F.sc, nslots * sizeof(Scalars), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int i = 0; i < nslots; ++i) {
+    const Scalars& v = c->host_sc[i];
+    int code;
+    switch (v.state) {
+      case ST_ACTIVE: code = 0; break;
+      case ST_FINISH:
+      case ST_DONE: code = (v.flags & FL_NOTCONV) ? 2 : 1; break;
+      case ST_FAILED: code = 3; break;
+      default: code = 4;
+    }
+    if (state_host) state_host[i] = code;
+    if (iters_host) iters_host[i] = v.iters;
+  }
+  return SPDE_OK;
+}
+
+spde_status spde_slot_finish(spde_handle h, int slot, double* u_box_dev, void* stream) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  spde_status s = check_ready(c);
+  if (s != SPDE_OK) return s;
+  if (slot < 0 || slot >= c->max_batch) return fail(SPDE_EINVAL, "slot out of range");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = pick_stream(c, stream);
+  HIPCHK(launch_fix_solution(c->F, c->box, 1, slot, st));
+  if (u_box_dev)
+    HIPCHK(hipMemcpyAsync(u_box_dev, c->F.x + cell_off(slot, c->box.nc), c->box.nc * 8, hipMemcpyDeviceToDevice,
+                          st));
+  HIPCHK(launch_set_state(c->F.sc, slot, 1, ST_IDLE, st));
+  return SPDE_OK;
+}
+
+spde_status spde_csr_apply(int64_t n_rows, int64_t nnz, const int64_t* rp, const int32_t* ci, const double* cv,
+                           int64_t n_cols, int batch, const double* x_dev, double* y_dev, void* stream) {
+  if (n_rows < 1 || nnz < 0 || n_cols < 1 || batch < 1) return fail(SPDE_EINVAL, "invalid sizes");
+  if (!rp || !x_dev || !y_dev || (nnz > 0 && (!ci || !cv))) return fail(SPDE_EINVAL, "null pointer");
+  HIPCHK(launch_spmm(rp, ci, cv, x_dev, y_dev, n_rows, nnz, n_cols, batch, (hipStream_t)stream));
   return SPDE_OK;
 }
 

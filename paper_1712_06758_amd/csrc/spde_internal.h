@@ -122,7 +122,8 @@ int tiles_for(int shape, int m);
 int operator_blocks(const Box& bx);
 
 hipError_t launch_init(const Fields& F, const Box& bx, const double* xi, double scale, int batch, double tol,
-                       int max_iter, hipStream_t st);
+                       int max_iter, int slot0, hipStream_t st);
+hipError_t launch_set_state(Scalars* sc, int slot0, int count, int state, hipStream_t st);
 hipError_t launch_mg_down(bool fp64, int shape, bool fine, const void* b0, const void* b1, void* rH,
                           const Level& L, int batch, const Scalars* sc, hipStream_t st);
 hipError_t launch_mg_up(bool fp64, int shape, bool fine, const void* b0, const void* b1, const void* eH, void* o0,
@@ -133,7 +134,7 @@ hipError_t launch_mg_coarse(bool fp64, const void* btop, void* etop, const Coars
                             int batch, const Scalars* sc, hipStream_t st);
 hipError_t launch_scalar(const Fields& F, int nb_up, int nb_pb, int batch, hipStream_t st);
 hipError_t launch_operator(bool z_fp64, const Fields& F, const Box& bx, int batch, hipStream_t st);
-hipError_t launch_fix_solution(const Fields& F, const Box& bx, int batch, hipStream_t st);
+hipError_t launch_fix_solution(const Fields& F, const Box& bx, int batch, int slot0, hipStream_t st);
 hipError_t launch_flux(const double* u, double* sig_int, double* sig_ext, const Box& bx, int batch,
                        hipStream_t st);
 hipError_t launch_resid(const double* sig, const double* u, const double* xi, double scale, const Box& bx,

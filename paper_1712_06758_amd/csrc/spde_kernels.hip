@@ -69,12 +69,13 @@ struct Diag {
 // initialisation: v_1 = F = [0; scale * xi], state reset
 
 __global__ __launch_bounds__(kBlock) void k_init(Fields F, Box bx, const double* __restrict__ xi,
-                                                 double scale, int nb, double tol, int max_iter) {
-  const int slot = blockIdx.x / nb;
-  const int blk = blockIdx.x - slot * nb;
+                                                 double scale, int nb, double tol, int max_iter, int slot0) {
+  const int rel = blockIdx.x / nb;
+  const int slot = slot0 + rel;
+  const int blk = blockIdx.x - rel * nb;
   const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
   if (c < bx.nc) {
-    F.vu[1][cell_off(slot, bx.nc) + c] = scale * xi[cell_off(slot, bx.nc) + c];
+    F.vu[1][cell_off(slot, bx.nc) + c] = scale * xi[cell_off(rel, bx.nc) + c];
     F.vs[1][face_off(slot, 0, bx.nc) + c] = 0.0;
     F.vs[1][face_off(slot, 1, bx.nc) + c] = 0.0;
     F.vs[1][face_off(slot, 2, bx.nc) + c] = 0.0;
@@ -977,9 +978,16 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
 // ---------------------------------------------------------------------------
 // finishing
 
+// Slot states for continuous batching: set [slot0, slot0 + count) to `state`.
+__global__ void k_set_state(Scalars* sc, int slot0, int count, int state) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) sc[slot0 + i].state = state;
+}
+
 // Zero / NaN the solution of slots that finished with FL_ZERO / ST_FAILED.
-__global__ __launch_bounds__(kBlock) void k_fix_solution(Fields F, Box bx, int nb) {
-  const int slot = blockIdx.x / nb, blk = blockIdx.x - slot * nb;
+__global__ __launch_bounds__(kBlock) void k_fix_solution(Fields F, Box bx, int nb, int slot0) {
+  const int rel = blockIdx.x / nb, blk = blockIdx.x - rel * nb;
+  const int slot = slot0 + rel;
   const Scalars* S = F.sc + slot;
   const bool zero = S->flags & FL_ZERO;
   const bool fail = S->state == ST_FAILED;

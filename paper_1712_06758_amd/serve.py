@@ -1,0 +1,422 @@
+"""Continuous-batching request loop for a multilevel Monte Carlo driver.
+
+A request at level n asks for a coupled pair of Gaussian-field samples of the
+same random event (Sec. "Hierarchical SPDE sampler with non-matching mesh
+embedding"): the fine sample on the n^3 box and, unless n is the coarsest
+level, the coarse sample on the (n/2)^3 box driven by the restricted noise of
+eq. ml-linsys.  Both are projected onto the level's tet mesh.
+
+Each box size has one resident engine: a sampler handle (operators and
+multigrid hierarchy stay on the device), its own HIP stream and a pool of
+slots.  The loop
+  * moves arrived requests into per-engine FIFO queues,
+  * admits queued work into free slots while the HBM footprint of in-flight
+    work stays within the budget (continuous batching: slots are refilled
+    while the other slots keep iterating),
+  * enqueues a few MINRES iterations on every engine (the engines' streams run
+    concurrently on the device),
+  * polls, retires converged slots (field -> projection), and completes a
+    request when all its parts are done.
+The engine interface is small so that the scheduler can be exercised on the
+CPU with a simulated engine (tests/test_serve.py).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _abi
+from ._abi import SPDE_OK
+
+
+# ---------------------------------------------------------------------------
+# request bookkeeping
+
+
+@dataclass
+class Part:
+    req: "Request"
+    box_n: int                 # box edge this part is solved on
+    kind: str                  # "fine" or "coarse"
+    slot: int = -1
+    iters: int = 0
+    result: object = None      # u_tet tensor (GPU engine) or None
+
+
+@dataclass
+class Request:
+    rid: int
+    level: int
+    seed: tuple
+    t_arrival: float
+    parts: list = field(default_factory=list)
+    t_admit: float = -1.0
+    t_done: float = -1.0
+    footprint: int = 0
+    pending: int = 0
+    noise: object = None       # fine noise tensor (kept for verification when asked)
+
+
+def percentile(values, q):
+    """Nearest-rank percentile (q in [0, 100]) of a non-empty list."""
+    v = sorted(values)
+    k = max(0, min(len(v) - 1, int(math.ceil(q / 100.0 * len(v))) - 1))
+    return v[k]
+
+
+# ---------------------------------------------------------------------------
+# GPU engine
+
+
+class GpuEngine:
+    """One box size: a resident sampler handle, a stream and a slot pool."""
+
+    STATE_ACTIVE, STATE_DONE, STATE_NOTCONV, STATE_FAILED, STATE_IDLE = 0, 1, 2, 3, 4
+
+    def __init__(self, n, kappa, g, precision, slots, device, rtol=None, meshes=None, poll=4):
+        import torch
+        from . import Box
+        self.torch = torch
+        self.n = n
+        self.slots = slots
+        self.device = device
+        self.box = Box(n, kappa, g, precision=precision, rtol=rtol, max_batch=slots, device=device)
+        self.box.set_poll_interval(poll)
+        self.poll_iters = poll
+        self.stream = torch.cuda.Stream(device=device)
+        self.free = list(range(slots - 1, -1, -1))
+        self.busy = {}
+        self.transfers = {}           # mesh name -> (n_tet, nnz, rp, ci, cv)
+        for name, (xyz, tets) in (meshes or {}).items():
+            self.add_mesh(name, xyz, tets)
+        L = _abi.lib()
+        with torch.cuda.device(device), torch.cuda.stream(self.stream):
+            _abi.check(L.spde_slots_reset(self.box._hh.h, slots, self._sp()))
+        self.slot_bytes = self.box.info()["workspace_bytes"] // slots
+        self._state = np.zeros(slots, dtype=np.int32)
+        self._iters = np.zeros(slots, dtype=np.int32)
+        self._event = None
+
+    def _sp(self):
+        import ctypes as C
+        return C.c_void_p(self.stream.cuda_stream)
+
+    def add_mesh(self, name, xyz, tets):
+        from . import build_transfer_host
+        torch = self.torch
+        rp, ci, cv = build_transfer_host(self.n, xyz, tets)
+        d = self.device
+        self.transfers[name] = (tets.shape[0], ci.size, torch.as_tensor(rp).to(d),
+                                torch.as_tensor(ci).to(d), torch.as_tensor(cv).to(d))
+
+    def has_free(self):
+        return bool(self.free)
+
+    def start(self, part, xi):
+        import ctypes as C
+        slot = self.free.pop()
+        part.slot = slot
+        self.busy[slot] = part
+        with self.torch.cuda.device(self.device):
+            self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+            xi.record_stream(self.stream)
+            _abi.check(_abi.lib().spde_slot_start(self.box._hh.h, slot, C.c_void_p(xi.data_ptr()), self._sp()))
+
+    def step(self):
+        if not self.busy:
+            return
+        with self.torch.cuda.device(self.device):
+            _abi.check(_abi.lib().spde_slots_step(self.box._hh.h, self.slots, self.poll_iters, self._sp()))
+            self._event = self.torch.cuda.Event()
+            self._event.record(self.stream)
+
+    def ready(self):
+        """True when the last enqueued step has finished on the device."""
+        return self._event is None or self._event.query()
+
+    def poll(self):
+        """Finished parts (state != active) after the enqueued work."""
+        if not self.busy:
+            return []
+        L = _abi.lib()
+        with self.torch.cuda.device(self.device):
+            _abi.check(L.spde_slots_poll(self.box._hh.h, self.slots, self._state.ctypes.data,
+                                         self._iters.ctypes.data, self._sp()))
+        out = []
+        for slot, part in list(self.busy.items()):
+            st = int(self._state[slot])
+            if st != self.STATE_ACTIVE:
+                part.iters = int(self._iters[slot])
+                part.status = st
+                out.append(part)
+        return out
+
+    def finish(self, part, mesh):
+        """Field of a finished part projected onto `mesh`; frees the slot."""
+        import ctypes as C
+        torch = self.torch
+        L = _abi.lib()
+        n_tet, nnz, rp, ci, cv = self.transfers[mesh]
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            u = torch.empty(self.n ** 3, dtype=torch.float64, device=self.device)
+            ut = torch.empty(n_tet, dtype=torch.float64, device=self.device)
+            _abi.check(L.spde_slot_finish(self.box._hh.h, part.slot, C.c_void_p(u.data_ptr()), self._sp()))
+            _abi.check(L.spde_csr_apply(n_tet, nnz, C.c_void_p(rp.data_ptr()), C.c_void_p(ci.data_ptr()),
+                                        C.c_void_p(cv.data_ptr()), self.n ** 3, 1, C.c_void_p(u.data_ptr()),
+                                        C.c_void_p(ut.data_ptr()), self._sp()))
+        del self.busy[part.slot]
+        self.free.append(part.slot)
+        part.result = ut
+        return ut
+
+    def sync(self):
+        self.stream.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# the server
+
+
+class Server:
+    """Continuous-batching MLMC request loop over per-box-size engines.
+
+    engines: {box_n: engine}; every level n needs engines n and n/2 (except the
+    coarsest level).  hbm_budget: bytes of device memory that in-flight work may
+    claim (slot workspace share plus per-request noise and outputs)."""
+
+    def __init__(self, engines, levels, noise_fn, restrict_fn, hbm_budget, clock=time.perf_counter,
+                 keep_results=False):
+        self.engines = engines
+        self.levels = sorted(levels)
+        self.coarsest = self.levels[0]
+        self.noise_fn = noise_fn
+        self.restrict_fn = restrict_fn
+        self.hbm_budget = hbm_budget
+        self.clock = clock
+        self.keep_results = keep_results
+        self.queues = {n: deque() for n in engines}
+        self.in_flight = 0
+        self.peak_in_flight = 0
+        self.done = []
+        self.refused = 0
+        self.queue_depth = []
+
+    def parts_of(self, req):
+        parts = [Part(req, req.level, "fine")]
+        if req.level != self.coarsest:
+            parts.append(Part(req, req.level // 2, "coarse"))
+        return parts
+
+    def footprint(self, req):
+        b = 0
+        for p in req.parts:
+            e = self.engines[p.box_n]
+            b += e.slot_bytes + 2 * 8 * p.box_n ** 3
+        return b
+
+    def submit(self, level, seed, t_arrival, rid):
+        req = Request(rid, level, seed, t_arrival)
+        req.parts = self.parts_of(req)
+        req.footprint = self.footprint(req)
+        if req.footprint > self.hbm_budget:
+            self.refused += 1
+            return None
+        req.pending = len(req.parts)
+        # requests are admitted whole: queue the request at its fine engine
+        self.queues[level].append(req)
+        return req
+
+    def _slots_available(self, req):
+        need = {}
+        for p in req.parts:
+            need[p.box_n] = need.get(p.box_n, 0) + 1
+        return all(len(self.engines[n].free) >= k for n, k in need.items())
+
+    def _admit(self, now):
+        """Admit queued requests oldest-first across levels.  A request that does
+        not fit the HBM budget blocks admission (it is not bypassed, so large
+        requests cannot starve); one whose engine has no free slot lets younger
+        requests of other levels through."""
+        while True:
+            heads = sorted((q[0] for q in self.queues.values() if q), key=lambda r: (r.t_arrival, r.rid))
+            admitted = False
+            for req in heads:
+                if self.in_flight + req.footprint > self.hbm_budget:
+                    return
+                if not self._slots_available(req):
+                    continue
+                self.queues[req.level].popleft()
+                xi = self.noise_fn(req.level, req.seed)
+                if self.keep_results:
+                    req.noise = xi
+                self.engines[req.level].start(req.parts[0], xi)
+                if len(req.parts) == 2:
+                    xc = self.restrict_fn(xi, req.level)
+                    self.engines[req.level // 2].start(req.parts[1], xc)
+                req.t_admit = now
+                self.in_flight += req.footprint
+                self.peak_in_flight = max(self.peak_in_flight, self.in_flight)
+                admitted = True
+                break
+            if not admitted:
+                return
+
+    def _retire(self, e, t0):
+        for part in e.poll():
+            req = part.req
+            e.finish(part, req.level)
+            if not self.keep_results:
+                part.result = None
+            req.pending -= 1
+            if req.pending == 0:
+                e.sync()
+                req.t_done = self.clock() - t0
+                self.in_flight -= req.footprint
+                self.done.append(req)
+
+    def run(self, arrivals, time_limit=None, progress_every=None):
+        """Serve `arrivals`, a list of (t, level, request_index) sorted by t
+        (seconds after the start).  Each engine is polled, refilled and stepped
+        again as soon as its previous step has finished on the device, so small
+        boxes cycle at their own pace beside large ones."""
+        t0 = self.clock()
+        ai = 0
+        total = len(arrivals)
+        n_done0 = len(self.done)
+        next_report = progress_every
+        while len(self.done) - n_done0 < total - self.refused:
+            now = self.clock() - t0
+            if next_report is not None and now >= next_report:
+                print(f"[serve] t={now:.1f}s arrived={ai} done={len(self.done) - n_done0} "
+                      f"queued={sum(len(q) for q in self.queues.values())}", file=sys.stderr, flush=True)
+                next_report += progress_every
+            if time_limit is not None and now > time_limit:
+                break
+            while ai < total and arrivals[ai][0] <= now:
+                t, level, r = arrivals[ai]
+                self.submit(level, (level, r), t, ai)
+                ai += 1
+            progressed = False
+            for e in self.engines.values():
+                if e.busy and e.ready():
+                    self._retire(e, t0)
+                    progressed = True
+            self._admit(self.clock() - t0)
+            self.queue_depth.append((now, sum(len(q) for q in self.queues.values())))
+            for e in self.engines.values():
+                if e.busy and e.ready():
+                    e.step()
+                    progressed = True
+            if not progressed:
+                if ai < total and not any(e.busy for e in self.engines.values()) and \
+                        not any(self.queues.values()):
+                    wait = arrivals[ai][0] - (self.clock() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 0.005))
+                else:
+                    time.sleep(2e-5)
+        return self.report(self.clock() - t0, n_done0)
+
+    def report(self, wall, first=0):
+        done = self.done[first:]
+        out = {"wall_s": round(wall, 3), "completed": len(done), "refused": self.refused,
+               "peak_in_flight_bytes": self.peak_in_flight, "levels": {}}
+        samples = 0
+        for n in self.levels:
+            reqs = [r for r in done if r.level == n]
+            if not reqs:
+                continue
+            lat = [r.t_done - r.t_arrival for r in reqs]
+            wait = [r.t_admit - r.t_arrival for r in reqs]
+            it = [p.iters for r in reqs for p in r.parts]
+            samples += sum(len(r.parts) for r in reqs)
+            out["levels"][n] = {"requests": len(reqs), "p50_ms": round(1e3 * percentile(lat, 50), 3),
+                                "p99_ms": round(1e3 * percentile(lat, 99), 3),
+                                "mean_queue_wait_ms": round(1e3 * float(np.mean(wait)), 3),
+                                "mean_iters": round(float(np.mean(it)), 2),
+                                "requests_per_s": round(len(reqs) / wall, 2) if wall > 0 else 0.0}
+        out["samples_per_s"] = round(samples / wall, 2) if wall > 0 else 0.0
+        out["max_queue_depth"] = max((d for _, d in self.queue_depth), default=0)
+        return out
+
+
+# ---------------------------------------------------------------------------
+# GPU server construction and the command-line load run
+
+
+def device_noise(n, seed, device):
+    """Seeded N(0,1) noise on the device (the request's seed picks the stream)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed[0]) * 1000003 + int(seed[1]))
+    return torch.randn(n ** 3, dtype=torch.float64, device=device, generator=gen)
+
+
+def build_gpu_server(levels=(32, 64, 128, 256), corr_len=0.05, precision="mixed", slots=None,
+                     hbm_budget=None, device=None, keep_results=False, poll=4):
+    import torch
+    from . import g_unit_variance, restrict_noise
+    from workloads import serve_mesh
+    device = torch.device(device or "cuda:0")
+    kappa = 1.0 / corr_len
+    g = g_unit_variance(kappa)
+    levels = sorted(levels)
+    sizes = sorted(set(levels) | {n // 2 for n in levels if n != levels[0]})
+    default_slots = {16: 32, 32: 64, 64: 48, 128: 16, 256: 4}
+    slots = slots or {n: default_slots.get(n, 8) for n in sizes}
+    engines = {}
+    meshes = {n: serve_mesh(n) for n in levels}
+    for n in sizes:
+        need = {}
+        if n in levels:
+            need[n] = meshes[n]
+        if 2 * n in levels:
+            need[2 * n] = meshes[2 * n]
+        engines[n] = GpuEngine(n, kappa, g, precision, slots[n], device, meshes=need, poll=poll)
+    if hbm_budget is None:
+        hbm_budget = sum(e.slot_bytes * e.slots for e in engines.values()) + (8 << 30)
+
+    def noise_fn(level, seed):
+        return device_noise(level, seed, device)
+
+    def restrict_fn(xi, n):
+        return restrict_noise(xi.view(1, -1), n).view(-1)
+
+    return Server(engines, levels, noise_fn, restrict_fn, hbm_budget, keep_results=keep_results)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="MLMC serving load run (continuous batching)")
+    ap.add_argument("--duration", type=float, default=10.0, help="arrival window in seconds")
+    ap.add_argument("--scale", type=float, default=1.0, help="multiplier of the request rates")
+    ap.add_argument("--precision", default="mixed")
+    ap.add_argument("--levels", default="32,64,128,256")
+    ap.add_argument("--seed", type=int, default=2)
+    args = ap.parse_args(argv)
+    from workloads import SERVE_LEVELS, SERVE_CORR_LEN, poisson_arrivals
+    levels = [int(x) for x in args.levels.split(",")]
+    rates = {n: SERVE_LEVELS[n] * args.scale for n in levels}
+    srv = build_gpu_server(levels, SERVE_CORR_LEN, args.precision)
+    # warm-up: one request per level, not timed
+    warm = [(0.0, n, 10 ** 6 + i) for i, n in enumerate(levels)]
+    srv.run(warm)
+    srv.done.clear()
+    srv.queue_depth.clear()
+    arrivals = poisson_arrivals(rates, args.duration, seed=args.seed)
+    print(f"[serve] {len(arrivals)} requests over {args.duration} s at rate scale {args.scale}",
+          file=sys.stderr, flush=True)
+    rep = srv.run(arrivals, time_limit=args.duration * 4 + 30, progress_every=2.0)
+    rep["rates_per_s"] = rates
+    rep["precision"] = args.precision
+    print(json.dumps(rep), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,53 @@
+"""Serving on the GPU: continuous batching gives each request the same result
+alone and in the mix (bitwise), and the results match the oracle."""
+import numpy as np
+import pytest
+
+from oracle import noise, spectral as S, transfer as T
+from tests.gpu_common import rel_l2, say
+from workloads import serve_mesh
+
+pytestmark = pytest.mark.gpu
+
+
+def test_alone_equals_mix_and_oracle():
+    import torch
+    from paper_1712_06758_amd.serve import build_gpu_server
+    say("serving alone vs mix, levels 32/64")
+    levels = (32, 64)
+    srv = build_gpu_server(levels, 0.05, "fp64", slots={32: 8, 64: 4}, keep_results=True, poll=2)
+    # 24 requests arriving together and over a short window: slots are refilled mid-flight
+    arr = sorted([(0.0, 32, i) for i in range(6)] + [(0.0, 64, 100 + i) for i in range(4)] +
+                 [(0.002 * i, 32 if i % 3 else 64, 200 + i) for i in range(14)])
+    rep = srv.run(arr, time_limit=120)
+    say(f"serving mix report {rep}")
+    assert rep["completed"] == len(arr)
+    mix = {r.seed: r for r in srv.done}
+    logged = sorted(mix)[:: max(1, len(mix) // 10)][:10]
+    alone = build_gpu_server(levels, 0.05, "fp64", slots={32: 8, 64: 4}, keep_results=True, poll=2)
+    for i, seed in enumerate(logged):
+        alone.run([(0.0, seed[0], seed[1])], time_limit=60)
+        a = alone.done[-1]
+        b = mix[seed]
+        assert a.seed == b.seed
+        for pa, pb in zip(a.parts, b.parts):
+            assert pa.kind == pb.kind
+            assert torch.equal(pa.result, pb.result), (seed, pa.kind)
+    # oracle check of two requests (fine and coupled coarse part, sampled tet rows)
+    kappa = 20.0
+    g = np.sqrt(8 * np.pi * kappa)
+    for seed in logged[:2]:
+        r = mix[seed]
+        n = r.level
+        xi = r.noise.cpu().numpy()
+        xyz, tets = serve_mesh(n)
+        rows = np.random.default_rng(0).choice(tets.shape[0], 60, replace=False)
+        u_f = S.solve_u(n, kappa, g, xi)
+        Pi = T.build_pi(xyz, tets, n, rows=rows)
+        got = r.parts[0].result.cpu().numpy()[rows]
+        assert np.abs(got - Pi @ u_f).max() <= 1e-9 * np.abs(Pi @ u_f).max()
+        if len(r.parts) == 2:
+            u_c = S.solve_u(n // 2, kappa, g, noise.restrict(n, xi))
+            Pc = T.build_pi(xyz, tets, n // 2, rows=rows)
+            got = r.parts[1].result.cpu().numpy()[rows]
+            assert np.abs(got - Pc @ u_c).max() <= 1e-9 * np.abs(Pc @ u_c).max()
