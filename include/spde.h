@@ -211,6 +211,14 @@ spde_status spde_apply_transfer(spde_handle h, int batch, const double* u_box_de
  * kernels one by one (0).  Results are bitwise identical either way. */
 spde_status spde_set_graphs(spde_handle h, int enable);
 
+/* Face (flux) block of the MINRES preconditioner: 0 = diag(M)^-1;
+ * 1 (default) = the truncated Neumann series q (I - S + S^2) of M^-1 along each
+ * grid line (M = (1/q)(I + S) on a line, q = 3/(2h^3)).  Both are symmetric
+ * positive definite; 1 takes about 20 % fewer iterations at no extra memory
+ * traffic.  The multigrid V-cycle on the approximate Schur complement
+ * kappa^2 W + B diag(M)^-1 B^T is the cell block in both cases. */
+spde_status spde_set_face_preconditioner(spde_handle h, int kind);
+
 /* Autotuning of the multigrid tile shapes (default on).  When on, the first
  * sample or V-cycle call of a handle times every admissible tile shape of each
  * per-level kernel at max_batch and keeps the fastest; the choice is shared by

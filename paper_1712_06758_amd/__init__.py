@@ -233,6 +233,10 @@ class Box:
     def set_poll_interval(self, k: int):
         _abi.check(_abi.lib().spde_set_poll_interval(self._hh.h, int(k)))
 
+    def set_face_preconditioner(self, kind: int):
+        """0: diag(M)^-1; 1: truncated Neumann series of M^-1 (default)."""
+        _abi.check(_abi.lib().spde_set_face_preconditioner(self._hh.h, int(kind)))
+
     def set_autotune(self, enable: bool):
         _abi.check(_abi.lib().spde_set_autotune(self._hh.h, int(bool(enable))))
 

@@ -39,6 +39,7 @@ SIGNATURES = {
     "spde_set_graphs": (C.c_int, [_vp, C.c_int]),
     "spde_set_poll_interval": (C.c_int, [_vp, C.c_int]),
     "spde_set_autotune": (C.c_int, [_vp, C.c_int]),
+    "spde_set_face_preconditioner": (C.c_int, [_vp, C.c_int]),
     "spde_get_tiles": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "spde_set_tiles": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int]),
     "spde_timing": (C.c_int, [_vp, C.c_int]),

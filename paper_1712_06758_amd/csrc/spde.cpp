@@ -109,6 +109,7 @@ struct Ctx {
   std::map<int, hipGraphExec_t> graphs;   // batch -> K-iteration graph
   bool tuned = false;
   bool autotune = true;
+  int face_precond = 1;          // 0 diag(M)^-1, 1 truncated Neumann series of M^-1
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -547,6 +548,7 @@ spde_status spde_configure(spde_handle h, spde_precision prec, double rtol, int 
   c->max_iter = max_iter;
   c->max_batch = max_batch;
   c->configured = true;
+  c->box.poly = c->face_precond;
   c->ws = nullptr;
   c->ws_bytes = 0;
   c->tuned = false;
@@ -837,10 +839,12 @@ spde_status spde_apply_operator(spde_handle h, int batch, const double* x_sigma_
   hipStream_t st = pick_stream(c, stream);
   Fields G = c->F;
   G.z[0] = G.w[0];            // a float64 cell buffer for zhat = x_u
-  HIPCHK(launch_ext_to_int(x_sigma_dev, x_u_dev, G, c->box, batch, st));
+  Box bd = c->box;
+  bd.poly = 0;                // face block diag(M)^-1: the pass then computes A x itself
+  HIPCHK(launch_ext_to_int(x_sigma_dev, x_u_dev, G, bd, batch, st));
   HIPCHK(launch_probe_scalars(G.sc, batch, st));
-  HIPCHK(launch_operator(true, G, c->box, batch, st));
-  HIPCHK(launch_int_to_ext(G, y_sigma_dev, y_u_dev, c->box, batch, st));
+  HIPCHK(launch_operator(true, G, bd, batch, st));
+  HIPCHK(launch_int_to_ext(G, y_sigma_dev, y_u_dev, bd, batch, st));
   return SPDE_OK;
 }
 
@@ -876,6 +880,16 @@ spde_status spde_set_graphs(spde_handle h, int enable) {
   Ctx* c = reinterpret_cast<Ctx*>(h);
   if (!c) return fail(SPDE_EINVAL, "null handle");
   c->use_graphs = enable != 0;
+  return SPDE_OK;
+}
+
+spde_status spde_set_face_preconditioner(spde_handle h, int kind) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (kind != 0 && kind != 1) return fail(SPDE_EINVAL, "face preconditioner must be 0 or 1");
+  c->face_precond = kind;
+  c->box.poly = kind;
+  drop_graphs(c);
   return SPDE_OK;
 }
 

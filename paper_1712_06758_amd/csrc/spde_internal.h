@@ -66,6 +66,7 @@ struct Box {
   double q;          // 3 / (2 h^3): inverse of the face diagonal of M
   double k2h3;       // kappa^2 h^3
   double h2q;        // h^2 q
+  int poly;          // face block of the preconditioner: 0 diag(M)^-1, 1 q (I - S + S^2)
 };
 
 // One multigrid level: operator S~ = k2 I + a L (L the Neumann graph

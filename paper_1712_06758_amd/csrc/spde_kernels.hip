@@ -66,6 +66,80 @@ struct Diag {
 };
 
 // ---------------------------------------------------------------------------
+// Face block of the preconditioner.
+//
+// On the interior faces of one grid line M = (1/q)(I + S), with q = 3/(2h^3)
+// and (S v)_g = (v_{g-1} + v_{g+1}) / 4 (boundary faces carry no unknown and
+// read as 0).  The face block of P^-1 is either diag(M)^-1 = q I, or the
+// truncated Neumann series q (I - S + S^2) of M^-1, which is symmetric
+// positive definite (eigenvalues of S lie in (-1/2, 1/2)) and needs no pass
+// of its own: along each line M P^-1 = I + S (diagonal) or I + S^3 (series).
+//
+// Given w[k] = v_{f+k}, k = -3..3 (f the low face of a cell, i its index along
+// the line, faces outside 1..n-1 zero), line_terms returns
+//   mz  = (M P^-1 v)_f,   zf = (P^-1 v)_f / q,   zh = (P^-1 v)_{f+1} / q.
+
+template <int R>
+__device__ __forceinline__ void line_load(const double* __restrict__ v, int64_t c, int64_t stride, int i, int n,
+                                          double* w) {
+#pragma unroll
+  for (int k = -3; k <= 3; ++k) {
+    const int g = i + k;
+    w[k + 3] = (k >= -R && k <= R && g >= 1 && g <= n - 1) ? v[c + k * stride] : 0.0;
+  }
+}
+
+__device__ __forceinline__ void line_terms(const double* w, int i, int n, int poly, double& mz, double& zf,
+                                           double& zh) {
+  if (!poly) {
+    mz = w[3] + 0.25 * (w[2] + w[4]);
+    zf = w[3];
+    zh = w[4];
+    return;
+  }
+  double s1[7], s2[7];
+#pragma unroll
+  for (int j = 1; j <= 5; ++j) {
+    const int g = i + j - 3;
+    s1[j] = (g >= 1 && g <= n - 1) ? 0.25 * (w[j - 1] + w[j + 1]) : 0.0;
+  }
+#pragma unroll
+  for (int j = 2; j <= 4; ++j) {
+    const int g = i + j - 3;
+    s2[j] = (g >= 1 && g <= n - 1) ? 0.25 * (s1[j - 1] + s1[j + 1]) : 0.0;
+  }
+  const bool fi = i >= 1, hi = i + 1 <= n - 1;
+  mz = w[3] + (fi ? 0.25 * (s2[2] + s2[4]) : 0.0);
+  zf = fi ? w[3] - s1[3] + s2[3] : 0.0;
+  zh = hi ? w[4] - s1[4] + s2[4] : 0.0;
+}
+
+// Per-cell contributions to gamma^2 = <P^-1 v, v> and delta gamma^2 =
+// <A P^-1 v, P^-1 v> (v = (v_sigma, v_u), P^-1 v = (.., zhat)) of the cell
+// with global index g, coordinates (x, y, z), on an n^3 box; vs is the slot's
+// face storage (three n^3 arrays), vu the cell value, zc = zhat at the cell.
+__device__ __forceinline__ void gamma_delta_terms(const double* __restrict__ vs, int64_t g, int x, int y, int z,
+                                                  const Box& bx, double vu, double zc, double& gg, double& dg) {
+  const int n = bx.n;
+  const int64_t nc = bx.nc;
+  const int idx[3] = {x, y, z};
+  const int64_t str[3] = {1, n, bx.n2};
+  double sv = 0.0, szm = 0.0, dv = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double w[7], mz, zf, zh;
+    if (bx.poly) line_load<3>(vs + d * nc, g, str[d], idx[d], n, w);
+    else line_load<1>(vs + d * nc, g, str[d], idx[d], n, w);
+    line_terms(w, idx[d], n, bx.poly, mz, zf, zh);
+    sv += zf * w[3];      // (P^-1 v)_f v_f / q
+    szm += zf * mz;       // (P^-1 v)_f (M P^-1 v)_f / q
+    dv += zh - zf;        // (B P^-1 v)_cell / (h^2 q)
+  }
+  gg += bx.q * sv + zc * vu;
+  dg += bx.q * szm + 2.0 * zc * bx.h2q * dv - bx.k2h3 * zc * zc;
+}
+
+// ---------------------------------------------------------------------------
 // initialisation: v_1 = F = [0; scale * xi], state reset
 
 __global__ __launch_bounds__(kBlock) void k_init(Fields F, Box bx, const double* __restrict__ xi,
@@ -330,21 +404,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_up(const TB* __restrict__ b0, con
     const int64_t g = gx + (int64_t)m * (gy + (int64_t)m * gz);
     const TO zo = (TO)out;
     o[g] = zo;
-    if (FINE && part) {
-      const double z = (double)zo;
-      const int64_t nc = bxc.nc;
-      const double* vx = vs + face_off(slot, 0, nc);
-      const double* vy = vs + face_off(slot, 1, nc);
-      const double* vz = vs + face_off(slot, 2, nc);
-      const double lox = vx[g], loy = vy[g], loz = vz[g];
-      const double hix = (gx < m - 1) ? vx[g + 1] : 0.0;
-      const double hiy = (gy < m - 1) ? vy[g + m] : 0.0;
-      const double hiz = (gz < m - 1) ? vz[g + (int64_t)m * m] : 0.0;
-      const double fq = lox * (lox + 0.5 * hix) + loy * (loy + 0.5 * hiy) + loz * (loz + 0.5 * hiz);
-      const double dv = (hix - lox) + (hiy - loy) + (hiz - loz);
-      p_zv += z * (double)b[g];
-      p_azz += bxc.q * fq + 2.0 * z * bxc.h2q * dv - bxc.k2h3 * z * z;
-    }
+    if (FINE && part)
+      gamma_delta_terms(vs + face_off(slot, 0, bxc.nc), g, gx, gy, gz, bxc, (double)b[g], (double)zo, p_zv, p_azz);
   }
   if (FINE && part) {
     p_zv = block_sum(p_zv, red);
@@ -556,22 +617,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_up_zs(const TB* __restrict__ b0, 
     for (int k = 0; k < PX::R; ++k) dst[k] = (eok[k] && zin) ? e[eoff[k] + mH2 * (z >> 1)] : (TM)0;
   };
   // face values for the partial sums of the output plane (fine level only)
-  // (pv: plane output at this step; pvn: plane output at the next step)
-  double pv[7] = {0, 0, 0, 0, 0, 0, 0}, pvn[7] = {0, 0, 0, 0, 0, 0, 0};
-  const int64_t nc = bxc.nc;
-  const double* vx = vs + face_off(slot, 0, nc);
-  const double* vy = vs + face_off(slot, 1, nc);
-  const double* vz = vs + face_off(slot, 2, nc);
-  auto fetch_v = [&](int z) {
-    if (FINE && part && own && (unsigned)z < (unsigned)m) {
-      const int64_t g = gx + (int64_t)m * gy + m2 * z;
-      pvn[0] = vx[g]; pvn[1] = vy[g]; pvn[2] = vz[g];
-      pvn[3] = (gx < m - 1) ? vx[g + 1] : 0.0;
-      pvn[4] = (gy < m - 1) ? vy[g + m] : 0.0;
-      pvn[5] = (z < m - 1) ? vz[g + m2] : 0.0;
-      pvn[6] = (double)b[g];
-    }
-  };
+  const double* vsl = vs + face_off(slot, 0, bxc.nc);
   const int zb = z0 - 3;
   const int nnxy = (gx > 0) + (gx < m - 1) + (gy > 0) + (gy < m - 1);
   double p_zv = 0.0, p_azz = 0.0;
@@ -590,7 +636,6 @@ __global__ __launch_bounds__(kBlock) void k_mg_up_zs(const TB* __restrict__ b0, 
     }
     if (s + 1 <= z1 + 2) fetch_b(s + 1);
     fetch_e(pe_next, s);        // corrections of plane s (used at the next step)
-    fetch_v(s - 2);             // faces of the plane output at the next step
     __syncthreads();
     const int zx = s - 1;
     if (zx >= z0 - 2) {
@@ -670,17 +715,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_up_zs(const TB* __restrict__ b0, 
       const int64_t g = gx + (int64_t)m * gy + m2 * zo;
       const TO zo_v = (TO)out;
       o[g] = zo_v;
-      if (FINE && part) {
-        const double z = (double)zo_v;
-        const double fq = pv[0] * (pv[0] + 0.5 * pv[3]) + pv[1] * (pv[1] + 0.5 * pv[4]) + pv[2] * (pv[2] + 0.5 * pv[5]);
-        const double dv = (pv[3] - pv[0]) + (pv[4] - pv[1]) + (pv[5] - pv[2]);
-        p_zv += z * pv[6];
-        p_azz += bxc.q * fq + 2.0 * z * bxc.h2q * dv - bxc.k2h3 * z * z;
-      }
-    }
-    if (FINE && part) {
-#pragma unroll
-      for (int k = 0; k < 7; ++k) pv[k] = pvn[k];
+      if (FINE && part) gamma_delta_terms(vsl, g, gx, gy, zo, bxc, (double)b[g], (double)zo_v, p_zv, p_azz);
     }
     __syncthreads();
   }
@@ -831,20 +866,16 @@ __global__ __launch_bounds__(kBlock) void k_scalar(Fields F, int nb_up, int nb_p
   }
   if (state != ST_ACTIVE) return;
   const int j = S->it;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  double a0 = 0.0, a1 = 0.0;
   const double* pu = F.part_up + (int64_t)slot * nb_up * 2;
   for (int i = threadIdx.x; i < nb_up; i += kBlock) { a0 += pu[2 * i]; a1 += pu[2 * i + 1]; }
-  if (j > 1) {
-    const double* pp = F.part_pb + (int64_t)slot * nb_pb;
-    for (int i = threadIdx.x; i < nb_pb; i += kBlock) a2 += pp[i];
-  }
   a0 = block_sum(a0, red);
   a1 = block_sum(a1, red);
-  a2 = block_sum(a2, red);
   if (threadIdx.x != 0) return;
+  (void)nb_pb;
 
   Scalars s = *S;
-  const double gg = a2 + a0;          // gamma_j^2
+  const double gg = a0;               // gamma_j^2
   if (!(gg >= 0.0) || !isfinite(gg) || !isfinite(a1)) {
     s.state = ST_FAILED; s.iters = j - 1; *S = s; return;
   }
@@ -894,17 +925,15 @@ __global__ __launch_bounds__(kBlock) void k_scalar(Fields F, int nb_up, int nb_p
 
 // ---------------------------------------------------------------------------
 // operator pass of iteration j:
-//   v_{j+1} = A z_j - a_v v_j - b_v v_{j-1},  z_j = (q v_sigma, zhat_u) / gamma_j
+//   v_{j+1} = A z_j - a_v v_j - b_v v_{j-1},  z_j = (P_sigma^-1 v_sigma, zhat_u) / gamma_j
 // and the delayed direction/solution update of step j-1.  One thread per
-// cell: the cell value and the three low faces of the cell.  With
-// z_sigma = q v_sigma, q h^3 = 3/2:
-//   (M z)_face = (v + (v_lo + v_hi) / 4) / gamma        (line tridiagonal)
+// cell: the cell value and the three low faces of the cell.
+//   (M z)_face = (M P_sigma^-1 v)_f / gamma              (line_terms)
 //   (B^T z_u)_face = h^2 (zhat[c - e_d] - zhat[c]) / gamma
-//   (A z)_cell = (h^2 q sum_d (v_hi - v_lo) - kappa^2 h^3 zhat) / gamma
+//   (A z)_cell = (h^2 q sum_d (z_hi - z_lo) / q - kappa^2 h^3 zhat) / gamma
 
 template <typename TZ>
 __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
-  __shared__ double red[kBlock / 64];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int slot = lb / nb, blk = lb - slot * nb;
   const Scalars* S = F.sc + slot;
@@ -916,62 +945,53 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
   const int n = bx.n;
   const int64_t n2 = bx.n2;
   const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
-  double ssig = 0.0;
-  if (c < nc) {
-    const int i = (int)(c % n), jj = (int)((c / n) % n), k = (int)(c / n2);
-    const int64_t co = cell_off(slot, nc);
-    if (state == ST_ACTIVE) {
-      const double zs = S->zs, av = S->a_v, bv = S->b_v;
-      const bool has_prev = j > 1;
-      const double* vx = F.vs[p] + face_off(slot, 0, nc);
-      const double* vy = F.vs[p] + face_off(slot, 1, nc);
-      const double* vz = F.vs[p] + face_off(slot, 2, nc);
-      const TZ* z = reinterpret_cast<const TZ*>(F.z[p]) + co;
-      const double zc = (double)z[c];
-      const double vxc = vx[c], vyc = vy[c], vzc = vz[c];
-      const double vxh = (i < n - 1) ? vx[c + 1] : 0.0;
-      const double vyh = (jj < n - 1) ? vy[c + n] : 0.0;
-      const double vzh = (k < n - 1) ? vz[c + n2] : 0.0;
-      const double Au = zs * (bx.h2q * ((vxh - vxc) + (vyh - vyc) + (vzh - vzc)) - bx.k2h3 * zc);
-      double Ax = 0.0, Ay = 0.0, Az = 0.0;
-      if (i > 0) Ax = zs * (vxc + 0.25 * (vx[c - 1] + vxh) + bx.h2 * ((double)z[c - 1] - zc));
-      if (jj > 0) Ay = zs * (vyc + 0.25 * (vy[c - n] + vyh) + bx.h2 * ((double)z[c - n] - zc));
-      if (k > 0) Az = zs * (vzc + 0.25 * (vz[c - n2] + vzh) + bx.h2 * ((double)z[c - n2] - zc));
-      double* ox = F.vs[pq] + face_off(slot, 0, nc);
-      double* oy = F.vs[pq] + face_off(slot, 1, nc);
-      double* oz = F.vs[pq] + face_off(slot, 2, nc);
-      double* ou = F.vu[pq] + co;
-      double nu = Au - av * F.vu[p][co + c];
-      double nx = Ax - av * vxc, ny = Ay - av * vyc, nz = Az - av * vzc;
-      if (has_prev) {
-        nu -= bv * ou[c];
-        nx -= bv * ox[c];
-        ny -= bv * oy[c];
-        nz -= bv * oz[c];
-      }
-      if (i == 0) nx = 0.0;
-      if (jj == 0) ny = 0.0;
-      if (k == 0) nz = 0.0;
-      ou[c] = nu; ox[c] = nx; oy[c] = ny; oz[c] = nz;
-      ssig = bx.q * (nx * nx + ny * ny + nz * nz);
-    }
-    const int wm = S->wmode;
-    if (wm >= 0) {
-      // w_j = wz zhat_{j-1} + ww_prev w_{j-2} + ww w_{j-1};  x_{j-1} = x_{j-2} + xw w_j
-      const TZ* zp = reinterpret_cast<const TZ*>(F.z[pq]) + co;
-      double* wj = F.w[p] + co;          // holds w_{j-2}, receives w_j
-      const double* w1 = F.w[pq] + co;   // w_{j-1}
-      double wn = S->wz * (double)zp[c];
-      if (wm >= 1) wn += S->ww * w1[c];
-      if (wm >= 2) wn += S->ww_prev * wj[c];
-      wj[c] = wn;
-      double* x = F.x + co;
-      x[c] = (wm == 0) ? S->xw * wn : x[c] + S->xw * wn;
-    }
-  }
+  if (c >= nc) return;
+  const int i = (int)(c % n), jj = (int)((c / n) % n), k = (int)(c / n2);
+  const int64_t co = cell_off(slot, nc);
   if (state == ST_ACTIVE) {
-    ssig = block_sum(ssig, red);
-    if (threadIdx.x == 0) F.part_pb[(int64_t)slot * nb + blk] = ssig;
+    const double zs = S->zs, av = S->a_v, bv = S->b_v;
+    const bool has_prev = j > 1;
+    const TZ* z = reinterpret_cast<const TZ*>(F.z[p]) + co;
+    const double zc = (double)z[c];
+    const int idx[3] = {i, jj, k};
+    const int64_t str[3] = {1, n, n2};
+    double dv = 0.0;
+    double nf[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double* v = F.vs[p] + face_off(slot, d, nc);
+      double w[7], mz, zf, zh;
+      if (bx.poly) line_load<3>(v, c, str[d], idx[d], n, w);
+      else line_load<1>(v, c, str[d], idx[d], n, w);
+      line_terms(w, idx[d], n, bx.poly, mz, zf, zh);
+      dv += zh - zf;
+      double a = 0.0;
+      if (idx[d] > 0) a = zs * (mz + bx.h2 * ((double)z[c - str[d]] - zc));
+      double* o = F.vs[pq] + face_off(slot, d, nc);
+      double nv = a - av * w[3];
+      if (has_prev) nv -= bv * o[c];
+      nf[d] = idx[d] > 0 ? nv : 0.0;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) F.vs[pq][face_off(slot, d, nc) + c] = nf[d];
+    const double Au = zs * (bx.h2q * dv - bx.k2h3 * zc);
+    double* ou = F.vu[pq] + co;
+    double nu = Au - av * F.vu[p][co + c];
+    if (has_prev) nu -= bv * ou[c];
+    ou[c] = nu;
+  }
+  const int wm = S->wmode;
+  if (wm >= 0) {
+    // w_j = wz zhat_{j-1} + ww_prev w_{j-2} + ww w_{j-1};  x_{j-1} = x_{j-2} + xw w_j
+    const TZ* zp = reinterpret_cast<const TZ*>(F.z[pq]) + co;
+    double* wj = F.w[p] + co;          // holds w_{j-2}, receives w_j
+    const double* w1 = F.w[pq] + co;   // w_{j-1}
+    double wn = S->wz * (double)zp[c];
+    if (wm >= 1) wn += S->ww * w1[c];
+    if (wm >= 2) wn += S->ww_prev * wj[c];
+    wj[c] = wn;
+    double* x = F.x + co;
+    x[c] = (wm == 0) ? S->xw * wn : x[c] + S->xw * wn;
   }
 }
 

@@ -218,3 +218,25 @@ def test_sample_with_tile_shape(torch_cuda, shape):
     u = out["u_box"].cpu().numpy()
     ref = oracle_u(w.n, w.kappa, w.g, xi)
     assert max(rel_l2(u[b], ref[b]) for b in range(2)) <= 1e-10
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-10), ("mixed", 1e-7)])
+def test_face_preconditioners(torch_cuda, prec, bar):
+    """Both face blocks of the preconditioner (diag(M)^-1 and the truncated
+    Neumann series of M^-1) reach the oracle; the series needs fewer iterations."""
+    torch = torch_cuda
+    w = WORKLOADS["box64"]
+    say(f"face preconditioners {prec} n=64")
+    xi = w.noise(3)
+    ref = oracle_u(w.n, w.kappa, w.g, xi)
+    iters = {}
+    for kind in (0, 1):
+        box = P().Box(w.n, w.kappa, precision=prec, max_batch=3)
+        box.set_face_preconditioner(kind)
+        out = box.sample(torch.tensor(xi, device="cuda"), u_box=True)
+        u = out["u_box"].cpu().numpy()
+        err = max(rel_l2(u[b], ref[b]) for b in range(3))
+        iters[kind] = int(out["iters"].max())
+        say(f"  kind {kind}: iters {out['iters'].tolist()} max err {err:.2e}")
+        assert err <= bar
+    assert iters[1] < iters[0]
