@@ -119,6 +119,17 @@ spde_status spde_set_transfer(spde_handle h, int64_t n_tet, int64_t nnz,
                               const int64_t* row_ptr_dev, const int32_t* col_dev,
                               const double* val_dev);
 
+/* Visiting order of the transfer SpMM: order_host [n_rows] receives the row
+ * indices sorted by their first column (cell index), so that neighbouring
+ * threads gather neighbouring cells.  Host-only; row_ptr/col as built above. */
+spde_status spde_transfer_row_order(int64_t n_rows, const int64_t* row_ptr_host,
+                                    const int32_t* col_host, int32_t* order_host);
+
+/* Register a device copy of such an order for the handle's transfer (borrowed;
+ * NULL restores the natural order).  Must follow spde_set_transfer.  Results
+ * do not depend on the order: each row is computed by one thread. */
+spde_status spde_set_transfer_order(spde_handle h, const int32_t* order_dev);
+
 /* ---- the sampler --------------------------------------------------------- */
 
 /* Draw `batch` field samples from the noise vectors xi_dev [batch][n^3]:
@@ -178,11 +189,13 @@ spde_status spde_slot_finish(spde_handle h, int slot, double* u_box_dev, void* s
 
 /* Stateless CSR SpMM y[b] = A x[b] for b < batch (the transfer apply with an
  * explicit matrix, Sec. "L2-Projection", eq. proj_op).  x [batch][n_cols],
- * y [batch][n_rows]; rows with indices outside [0, n_cols) skip them.
+ * y [batch][n_rows]; column indices outside [0, n_cols) are skipped; rows are
+ * visited in order_dev (see spde_transfer_row_order) when it is not NULL.
  * Asynchronous on `stream`. */
 spde_status spde_csr_apply(int64_t n_rows, int64_t nnz, const int64_t* row_ptr_dev,
                            const int32_t* col_dev, const double* val_dev, int64_t n_cols,
-                           int batch, const double* x_dev, double* y_dev, void* stream);
+                           int batch, const double* x_dev, double* y_dev,
+                           const int32_t* order_dev /* nullable */, void* stream);
 
 /* ---- operators exposed for verification -------------------------------- */
 

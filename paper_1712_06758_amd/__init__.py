@@ -94,6 +94,15 @@ def build_transfer_host(n: int, xyz: np.ndarray, tets: np.ndarray):
     return row_ptr, cols, vals
 
 
+def transfer_row_order(row_ptr, cols):
+    """Row visiting order of the transfer SpMM (rows sorted by first cell)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(cols, dtype=np.int32)
+    order = np.empty(rp.size - 1, dtype=np.int32)
+    _abi.check(_abi.lib().spde_transfer_row_order(order.size, rp.ctypes.data, ci.ctypes.data, order.ctypes.data))
+    return order
+
+
 def restrict_noise(xi_f, n_fine: int):
     """Noise of the coupled coarse sample: [B, n^3] -> [B, (n/2)^3] on the device."""
     torch = _torch()
@@ -150,10 +159,14 @@ class Box:
         rp = torch.as_tensor(np.asarray(row_ptr, dtype=np.int64)).to(d)
         ci = torch.as_tensor(np.asarray(cols, dtype=np.int32)).to(d)
         cv = torch.as_tensor(np.asarray(vals, dtype=np.float64)).to(d)
-        self._pi = (rp, ci, cv)
+        order = transfer_row_order(row_ptr, cols)
+        od = torch.as_tensor(order).to(d)
+        self._pi = (rp, ci, cv, od)
         self.n_tet = rp.numel() - 1
         self.nnz = ci.numel()
-        _abi.check(_abi.lib().spde_set_transfer(self._hh.h, self.n_tet, self.nnz, _ptr(rp), _ptr(ci), _ptr(cv)))
+        L = _abi.lib()
+        _abi.check(L.spde_set_transfer(self._hh.h, self.n_tet, self.nnz, _ptr(rp), _ptr(ci), _ptr(cv)))
+        _abi.check(L.spde_set_transfer_order(self._hh.h, _ptr(od)))
         return self.n_tet, self.nnz
 
     # -- sampling ---------------------------------------------------------

@@ -52,7 +52,9 @@ SIGNATURES = {
     "spde_slots_step": (C.c_int, [_vp, C.c_int, C.c_int, _vp]),
     "spde_slots_poll": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "spde_slot_finish": (C.c_int, [_vp, C.c_int, _vp, _vp]),
-    "spde_csr_apply": (C.c_int, [C.c_int64, C.c_int64, _vp, _vp, _vp, C.c_int64, C.c_int, _vp, _vp, _vp]),
+    "spde_csr_apply": (C.c_int, [C.c_int64, C.c_int64, _vp, _vp, _vp, C.c_int64, C.c_int, _vp, _vp, _vp, _vp]),
+    "spde_transfer_row_order": (C.c_int, [C.c_int64, _vp, _vp, _vp]),
+    "spde_set_transfer_order": (C.c_int, [_vp, _vp]),
     "spde_free_host": (None, [_vp]),
     "spde_destroy": (None, [_vp]),
     "spde_last_error": (C.c_char_p, []),

@@ -103,6 +103,7 @@ struct Ctx {
   const int64_t* rp = nullptr;
   const int32_t* ci = nullptr;
   const double* cv = nullptr;
+  const int32_t* order = nullptr;   // optional row visiting order of the SpMM
   // execution
   bool use_graphs = true;
   int poll = 8;
@@ -244,9 +245,16 @@ double slot_bytes(const Ctx* c, int kid, int level, int iter, int wmode_active) 
   const double nc = (double)c->box.nc, sz = (double)c->szm();
   switch (kid) {
     case KID_OPERATOR: {
+      // v update: read v_j (faces 24, cell 8), v_{j-1} (32, from j = 2), zhat_j; write v_{j+1} (32)
+      // w/x update: read zhat_{j-1}, w_{j-1} (j >= 3), w_{j-2} (j >= 4); write w_j; x read+write on
+      // even passes and on the finishing pass, x write only at j = 2
       double b = 0;
-      if (wmode_active & 1) b += nc * ((iter > 1 ? 64.0 : 32.0) + sz + 32.0);   // v update
-      if (wmode_active & 2) b += nc * (sz + 16.0 + (iter >= 3 ? 8.0 : 0.0) + (iter >= 4 ? 16.0 : 0.0));
+      if (wmode_active & 1) b += nc * ((iter > 1 ? 64.0 : 32.0) + sz + 32.0);
+      if (wmode_active & 2) {
+        b += nc * (sz + 8.0 + (iter >= 3 ? 8.0 : 0.0) + (iter >= 4 ? 8.0 : 0.0));
+        if (iter == 2) b += nc * 8.0;
+        else if ((iter % 2) == 0 || (wmode_active & 4)) b += nc * 16.0;
+      }
       return b;
     }
     case KID_MG_UP_FINE: return nc * (8.0 + sz / 8.0 + 24.0 + sz);
@@ -356,6 +364,7 @@ void close_timing(Ctx* c, int batch) {
         int mode = 0;
         if (r.iter <= J) mode |= 1;
         if (r.iter >= 2 && r.iter <= J + 1) mode |= 2;
+        if (r.iter == J + 1) mode |= 4;
         bytes += slot_bytes(c, r.kid, 0, r.iter, mode);
       } else if (r.iter >= 1 && r.iter <= J + 1) {
         bytes += slot_bytes(c, r.kid, r.level, r.iter, 0);
@@ -624,6 +633,7 @@ spde_status spde_set_transfer(spde_handle h, int64_t n_tet, int64_t nnz, const i
     return fail(SPDE_EINVAL, "invalid transfer matrix");
   c->n_tet = n_tet;
   c->nnz = nnz;
+  c->order = nullptr;
   c->rp = row_ptr_dev;
   c->ci = col_dev;
   c->cv = val_dev;
@@ -703,7 +713,7 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* 
   }
   if (u_tet_dev) {
     Timed t(c, KID_SPMM, 0, st);
-    HIPCHK(launch_spmm(c->rp, c->ci, c->cv, c->F.x, u_tet_dev, c->n_tet, c->nnz, bx.nc, batch, st));
+    HIPCHK(launch_spmm(c->rp, c->ci, c->cv, c->F.x, u_tet_dev, c->n_tet, c->nnz, bx.nc, batch, c->order, st));
   }
   if (relres_host || c->timing) {
     HIPCHK(hipStreamSynchronize(st));
@@ -813,10 +823,11 @@ spde_status spde_slot_finish(spde_handle h, int slot, double* u_box_dev, void* s
 }
 
 spde_status spde_csr_apply(int64_t n_rows, int64_t nnz, const int64_t* rp, const int32_t* ci, const double* cv,
-                           int64_t n_cols, int batch, const double* x_dev, double* y_dev, void* stream) {
+                           int64_t n_cols, int batch, const double* x_dev, double* y_dev,
+                           const int32_t* order_dev, void* stream) {
   if (n_rows < 1 || nnz < 0 || n_cols < 1 || batch < 1) return fail(SPDE_EINVAL, "invalid sizes");
   if (!rp || !x_dev || !y_dev || (nnz > 0 && (!ci || !cv))) return fail(SPDE_EINVAL, "null pointer");
-  HIPCHK(launch_spmm(rp, ci, cv, x_dev, y_dev, n_rows, nnz, n_cols, batch, (hipStream_t)stream));
+  HIPCHK(launch_spmm(rp, ci, cv, x_dev, y_dev, n_rows, nnz, n_cols, batch, order_dev, (hipStream_t)stream));
   return SPDE_OK;
 }
 
@@ -871,8 +882,29 @@ spde_status spde_apply_transfer(spde_handle h, int batch, const double* u_box_de
   if (!c->rp) return fail(SPDE_EINVAL, "no transfer set");
   if (batch < 1 || !u_box_dev || !u_tet_dev) return fail(SPDE_EINVAL, "invalid argument");
   if (c->device >= 0) HIPCHK(hipSetDevice(c->device));
-  HIPCHK(launch_spmm(c->rp, c->ci, c->cv, u_box_dev, u_tet_dev, c->n_tet, c->nnz, c->box.nc, batch,
+  HIPCHK(launch_spmm(c->rp, c->ci, c->cv, u_box_dev, u_tet_dev, c->n_tet, c->nnz, c->box.nc, batch, c->order,
                      (hipStream_t)stream));
+  return SPDE_OK;
+}
+
+spde_status spde_transfer_row_order(int64_t n_rows, const int64_t* row_ptr_host, const int32_t* col_host,
+                                    int32_t* order_host) {
+  if (n_rows < 1 || n_rows > INT32_MAX || !row_ptr_host || !order_host) return fail(SPDE_EINVAL, "invalid argument");
+  std::vector<std::pair<int64_t, int32_t>> key(n_rows);
+  for (int64_t r = 0; r < n_rows; ++r) {
+    const int64_t k0 = row_ptr_host[r], k1 = row_ptr_host[r + 1];
+    key[r] = {(k1 > k0 && col_host) ? (int64_t)col_host[k0] : INT64_MAX, (int32_t)r};
+  }
+  std::stable_sort(key.begin(), key.end());
+  for (int64_t r = 0; r < n_rows; ++r) order_host[r] = key[r].second;
+  return SPDE_OK;
+}
+
+spde_status spde_set_transfer_order(spde_handle h, const int32_t* order_dev) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (!c->rp) return fail(SPDE_EINVAL, "no transfer set");
+  c->order = order_dev;
   return SPDE_OK;
 }
 

@@ -45,6 +45,7 @@ struct alignas(16) Scalars {
   double b_v;                 // gamma_j / gamma_{j-1}
   double wz, ww_prev, ww;     // w_j = wz zhat_{j-1} + ww_prev w_{j-2} + ww w_{j-1}
   double xw;                  // x_{j-1} = x_{j-2} + xw w_j
+  double xpend;               // coefficient of w_{j-1} whose x update was deferred (0 if none)
   double tol;                 // relative stopping tolerance on |eta| / eta0
   int it;                     // iteration the V-cycle and the scalar step work on
   int pit;                    // iteration the operator pass works on
@@ -141,7 +142,7 @@ hipError_t launch_flux(const double* u, double* sig_int, double* sig_ext, const 
 hipError_t launch_resid(const double* sig, const double* u, const double* xi, double scale, const Box& bx,
                         int batch, double* part, double* out, hipStream_t st);
 hipError_t launch_spmm(const int64_t* rp, const int32_t* ci, const double* cv, const double* u, double* out,
-                       int64_t ntet, int64_t nnz, int64_t nc, int batch, hipStream_t st);
+                       int64_t ntet, int64_t nnz, int64_t nc, int batch, const int32_t* order, hipStream_t st);
 hipError_t launch_restrict_noise(const double* xf, double* xc, int nf, int batch, hipStream_t st);
 hipError_t launch_ext_to_int(const double* xs, const double* xu, const Fields& F, const Box& bx, int batch,
                              hipStream_t st);

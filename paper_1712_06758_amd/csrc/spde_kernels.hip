@@ -97,6 +97,16 @@ __device__ __forceinline__ void line_terms(const double* w, int i, int n, int po
     zh = w[4];
     return;
   }
+  if (i >= 4 && i <= n - 4) {
+    // all faces f-3..f+3 interior: the series collapses to fixed stencils
+    //   (P^-1 v)_f / q = 9/8 v_f - (v_{f-1} + v_{f+1}) / 4 + (v_{f-2} + v_{f+2}) / 16
+    //   (M P^-1 v)_f   = v_f + (v_{f-3} + v_{f+3} + 3 (v_{f-1} + v_{f+1})) / 64
+    const double a = w[2] + w[4];
+    zf = 1.125 * w[3] - 0.25 * a + 0.0625 * (w[1] + w[5]);
+    zh = 1.125 * w[4] - 0.25 * (w[3] + w[5]) + 0.0625 * (w[2] + w[6]);
+    mz = w[3] + 0.015625 * ((w[0] + w[6]) + 3.0 * a);
+    return;
+  }
   double s1[7], s2[7];
 #pragma unroll
   for (int j = 1; j <= 5; ++j) {
@@ -118,6 +128,27 @@ __device__ __forceinline__ void line_terms(const double* w, int i, int n, int po
 // <A P^-1 v, P^-1 v> (v = (v_sigma, v_u), P^-1 v = (.., zhat)) of the cell
 // with global index g, coordinates (x, y, z), on an n^3 box; vs is the slot's
 // face storage (three n^3 arrays), vu the cell value, zc = zhat at the cell.
+// The same contributions from line values already gathered (wx, wy, wz hold
+// v_{f+k}, k = -3..3, along x, y, z; zero outside the interior faces).
+__device__ __forceinline__ void gamma_delta_lines(const double* wx, const double* wy, const double* wz, int x, int y,
+                                                  int z, const Box& bx, double vu, double zc, double& gg,
+                                                  double& dg) {
+  const int n = bx.n;
+  const double* ws[3] = {wx, wy, wz};
+  const int idx[3] = {x, y, z};
+  double sv = 0.0, szm = 0.0, dv = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double mz, zf, zh;
+    line_terms(ws[d], idx[d], n, bx.poly, mz, zf, zh);
+    sv += zf * ws[d][3];
+    szm += zf * mz;
+    dv += zh - zf;
+  }
+  gg += bx.q * sv + zc * vu;
+  dg += bx.q * szm + 2.0 * zc * bx.h2q * dv - bx.k2h3 * zc * zc;
+}
+
 __device__ __forceinline__ void gamma_delta_terms(const double* __restrict__ vs, int64_t g, int x, int y, int z,
                                                   const Box& bx, double vu, double zc, double& gg, double& dg) {
   const int n = bx.n;
@@ -544,7 +575,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_down_zs(const TB* __restrict__ b0
 }
 
 template <typename TM, typename TB, typename TO, int TX, int TY, int ZC, bool FINE>
-__global__ __launch_bounds__(kBlock) void k_mg_up_zs(const TB* __restrict__ b0, const TB* __restrict__ b1,
+__global__ __launch_bounds__(kBlock, 4) void k_mg_up_zs(const TB* __restrict__ b0, const TB* __restrict__ b1,
                                                      const TM* __restrict__ eH, TO* __restrict__ o0,
                                                      TO* __restrict__ o1, Level L, int nb,
                                                      const Scalars* __restrict__ sc,
@@ -559,6 +590,11 @@ __global__ __launch_bounds__(kBlock) void k_mg_up_zs(const TB* __restrict__ b0, 
   __shared__ TM sx[4][PX::A];
   __shared__ TM sy[3][PY::A];
   __shared__ double red[kBlock / 64];
+  // fine level: the x- and y-face planes of the output plane (radius 3 along the line)
+  constexpr int FXW = TX + 6, FXA = FINE ? FXW * TY : 1, FYA = FINE ? TX * (TY + 6) : 1;
+  constexpr int FXR = (FXA + kBlock - 1) / kBlock, FYR = (FYA + kBlock - 1) / kBlock;
+  __shared__ double fxp[FXA];
+  __shared__ double fyp[FYA];
   const int m = L.m;
   const int64_t m2 = (int64_t)m * m;
   const int tpx = (m + TX - 1) / TX, tpy = (m + TY - 1) / TY;
@@ -618,10 +654,35 @@ __global__ __launch_bounds__(kBlock) void k_mg_up_zs(const TB* __restrict__ b0, 
   };
   // face values for the partial sums of the output plane (fine level only)
   const double* vsl = vs + face_off(slot, 0, bxc.nc);
+  const bool parts = FINE && part != nullptr;
+  double pfx[FXR], pfy[FYR];
+  double wzl[7] = {0, 0, 0, 0, 0, 0, 0}, wz_next = 0.0;
+  auto fetch_faces = [&](int z) {
+    if (!parts) return;
+    const bool zin = (unsigned)z < (unsigned)m;
+#pragma unroll
+    for (int k = 0; k < FXR; ++k) {
+      const int p = threadIdx.x + k * kBlock;
+      const int hx = x0 + p % FXW - 3, hy = y0 + p / FXW;
+      pfx[k] = (p < FXA && zin && hx >= 1 && hx <= m - 1 && hy < m) ? vsl[hx + (int64_t)m * hy + m2 * z] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < FYR; ++k) {
+      const int p = threadIdx.x + k * kBlock;
+      const int hx = x0 + p % TX, hy = y0 + p / TX - 3;
+      pfy[k] = (p < FYA && zin && hx < m && hy >= 1 && hy <= m - 1)
+                   ? vsl[bxc.nc + hx + (int64_t)m * hy + m2 * z] : 0.0;
+    }
+  };
+  auto fetch_wz = [&](int z) {
+    wz_next = (parts && own && z >= 1 && z <= m - 1) ? vsl[2 * bxc.nc + gx + (int64_t)m * gy + m2 * z] : 0.0;
+  };
   const int zb = z0 - 3;
   const int nnxy = (gx > 0) + (gx < m - 1) + (gy > 0) + (gy < m - 1);
   double p_zv = 0.0, p_azz = 0.0;
   fetch_b(zb);
+  fetch_faces(zb - 3);
+  fetch_wz(zb);
 #pragma unroll
   for (int k = 0; k < PX::R; ++k) pe[k] = 0;
   for (int s = zb; s <= z1 + 2; ++s) {
@@ -633,6 +694,24 @@ __global__ __launch_bounds__(kBlock) void k_mg_up_zs(const TB* __restrict__ b0, 
         const int p = threadIdx.x + k * kBlock;
         if (p < PB::A) bs[p] = (TM)pf[k] * D.inv(bnn[k] + zn);
       }
+    }
+    if (parts) {
+      // face planes of the output plane s-3 into LDS; z-faces slide through registers
+#pragma unroll
+      for (int k = 0; k < FXR; ++k) {
+        const int p = threadIdx.x + k * kBlock;
+        if (p < FXA) fxp[p] = pfx[k];
+      }
+#pragma unroll
+      for (int k = 0; k < FYR; ++k) {
+        const int p = threadIdx.x + k * kBlock;
+        if (p < FYA) fyp[p] = pfy[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) wzl[k] = wzl[k + 1];
+      wzl[6] = wz_next;
+      fetch_faces(s - 2);
+      fetch_wz(s + 1);
     }
     if (s + 1 <= z1 + 2) fetch_b(s + 1);
     fetch_e(pe_next, s);        // corrections of plane s (used at the next step)
@@ -715,7 +794,15 @@ __global__ __launch_bounds__(kBlock) void k_mg_up_zs(const TB* __restrict__ b0, 
       const int64_t g = gx + (int64_t)m * gy + m2 * zo;
       const TO zo_v = (TO)out;
       o[g] = zo_v;
-      if (FINE && part) gamma_delta_terms(vsl, g, gx, gy, zo, bxc, (double)b[g], (double)zo_v, p_zv, p_azz);
+      if (parts) {
+        double wx[7], wy[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          wx[k] = fxp[tx + k + FXW * ty];
+          wy[k] = fyp[tx + TX * (ty + k)];
+        }
+        gamma_delta_lines(wx, wy, wzl, gx, gy, zo, bxc, (double)b[g], (double)zo_v, p_zv, p_azz);
+      }
     }
     __syncthreads();
   }
@@ -901,6 +988,9 @@ __global__ __launch_bounds__(kBlock) void k_scalar(Fields F, int nb_up, int nb_p
     s.wz = 1.0 / (al1 * gp);
     s.ww_prev = -al3 / al1;
     s.ww = -al2 / al1;
+    // the operator pass of an odd iteration >= 3 defers its solution update to
+    // the next pass (x absorbs two directions every other iteration)
+    s.xpend = ((j - 1) % 2 == 1 && j - 1 >= 3) ? s.xw : 0.0;
     s.xw = cn * s.eta;
     s.eta = -sn * s.eta;
     s.c_prev = s.c; s.s_prev = s.s;
@@ -986,12 +1076,18 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
     const TZ* zp = reinterpret_cast<const TZ*>(F.z[pq]) + co;
     double* wj = F.w[p] + co;          // holds w_{j-2}, receives w_j
     const double* w1 = F.w[pq] + co;   // w_{j-1}
+    double w1c = 0.0;
     double wn = S->wz * (double)zp[c];
-    if (wm >= 1) wn += S->ww * w1[c];
+    if (wm >= 1) { w1c = w1[c]; wn += S->ww * w1c; }
     if (wm >= 2) wn += S->ww_prev * wj[c];
     wj[c] = wn;
-    double* x = F.x + co;
-    x[c] = (wm == 0) ? S->xw * wn : x[c] + S->xw * wn;
+    // x is written on even iterations and on the finishing pass; an odd
+    // iteration leaves its term to the next pass (coefficient xpend of w_{j-1})
+    if ((j & 1) == 0 || state == ST_FINISH || wm == 0) {
+      double* x = F.x + co;
+      const double inc = S->xpend * w1c + S->xw * wn;
+      x[c] = (wm == 0) ? inc : x[c] + inc;
+    }
   }
 }
 
@@ -1137,10 +1233,14 @@ template <int NR>
 __global__ __launch_bounds__(kBlock) void k_spmm(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                  const double* __restrict__ cv, const double* __restrict__ u,
                                                  double* __restrict__ out, int64_t ntet, int64_t nnz, int64_t nc,
-                                                 int batch) {
-  const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+                                                 int batch, const int32_t* __restrict__ order) {
+  const int64_t pos = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int s0 = blockIdx.y * NR;
-  if (row >= ntet) return;
+  if (pos >= ntet) return;
+  // rows are visited in `order` (if given) so that neighbouring threads gather
+  // neighbouring cells; an out-of-range entry is skipped
+  const int64_t row = order ? (int64_t)order[pos] : pos;
+  if (row < 0 || row >= ntet) return;
   const int nr = min(NR, batch - s0);
   double acc[NR];
 #pragma unroll
@@ -1230,7 +1330,7 @@ __global__ void k_probe_scalars(Scalars* sc, int batch) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= batch) return;
   Scalars v{};
-  v.state = ST_ACTIVE; v.pit = 0; v.it = 0; v.zs = 1.0; v.a_v = 0.0; v.b_v = 0.0; v.wmode = -1;
+  v.state = ST_ACTIVE; v.pit = 0; v.it = 0; v.zs = 1.0; v.a_v = 0.0; v.b_v = 0.0; v.wmode = -1; v.xpend = 0.0;
   sc[s] = v;
 }
 

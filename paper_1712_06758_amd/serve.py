@@ -109,12 +109,13 @@ class GpuEngine:
         return C.c_void_p(self.stream.cuda_stream)
 
     def add_mesh(self, name, xyz, tets):
-        from . import build_transfer_host
+        from . import build_transfer_host, transfer_row_order
         torch = self.torch
         rp, ci, cv = build_transfer_host(self.n, xyz, tets)
         d = self.device
         self.transfers[name] = (tets.shape[0], ci.size, torch.as_tensor(rp).to(d),
-                                torch.as_tensor(ci).to(d), torch.as_tensor(cv).to(d))
+                                torch.as_tensor(ci).to(d), torch.as_tensor(cv).to(d),
+                                torch.as_tensor(transfer_row_order(rp, ci)).to(d))
 
     def has_free(self):
         return bool(self.free)
@@ -163,14 +164,14 @@ class GpuEngine:
         import ctypes as C
         torch = self.torch
         L = _abi.lib()
-        n_tet, nnz, rp, ci, cv = self.transfers[mesh]
+        n_tet, nnz, rp, ci, cv, od = self.transfers[mesh]
         with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
             u = torch.empty(self.n ** 3, dtype=torch.float64, device=self.device)
             ut = torch.empty(n_tet, dtype=torch.float64, device=self.device)
             _abi.check(L.spde_slot_finish(self.box._hh.h, part.slot, C.c_void_p(u.data_ptr()), self._sp()))
             _abi.check(L.spde_csr_apply(n_tet, nnz, C.c_void_p(rp.data_ptr()), C.c_void_p(ci.data_ptr()),
                                         C.c_void_p(cv.data_ptr()), self.n ** 3, 1, C.c_void_p(u.data_ptr()),
-                                        C.c_void_p(ut.data_ptr()), self._sp()))
+                                        C.c_void_p(ut.data_ptr()), C.c_void_p(od.data_ptr()), self._sp()))
         del self.busy[part.slot]
         self.free.append(part.slot)
         part.result = ut
