@@ -78,21 +78,54 @@ def vcycle_gbs(rep):
     return round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 else None
 
 
-def cpu_baseline(n, kappa, g, xi_np, count):
-    """The oracle (spectral exact solve) on `count` right-hand sides of the workload."""
+def cpu_baseline(n, kappa, g, xi_np):
+    """The oracle on the machine's host cores: its block-preconditioned MINRES route
+    (the method, with the exact DCT Schur preconditioner, to the same relative
+    tolerance as the float64 GPU path) on one noise vector of the workload, and
+    its closed-form spectral solve on all of them."""
     import oracle
-    t0 = time.perf_counter()
-    for b in range(count):
-        oracle.sample_box(n, kappa, g, xi_np[b])
-    dt = time.perf_counter() - t0
+    from oracle import discretize, minres
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
-    return {"value": round(count / dt, 4), "unit": "samples/s", "cores": cores, "kind": "oracle",
-            "sample": f"{count} of the 64 noise vectors of the 128^3 workload through the oracle's "
-                      f"exact spectral box solve (scipy.fft, workers=-1); {dt:.1f} s of CPU time; the "
-                      f"transfer apply (<1% of the work) not included"}
+    ops = discretize.assemble(n)
+    F = discretize.rhs(ops, g, xi_np[0])
+    t0 = time.perf_counter()
+    _, _, it = minres.solve(ops, kappa, F, tol=3e-11)
+    t_minres = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for b in range(xi_np.shape[0]):
+        oracle.sample_box(n, kappa, g, xi_np[b])
+    t_spec = time.perf_counter() - t0
+    return {"value": round(1.0 / t_minres, 5), "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 of the 64 noise vectors of the {n}^3 workload through the oracle's preconditioned "
+                      f"MINRES (SciPy sparse operator, exact DCT Schur preconditioner, rtol 3e-11, {it} "
+                      f"iterations): {t_minres:.1f} s; transfer apply not included",
+            "spectral_exact_samples_per_s": round(xi_np.shape[0] / t_spec, 3),
+            "spectral_note": f"closed-form DCT solve (valid only for this constant-coefficient box), "
+                             f"{xi_np.shape[0]} vectors in {t_spec:.1f} s"}
+
+
+def serving_run(seconds, scale):
+    """MLMC serving load: levels 32/64/128/256 with Poisson arrivals in the
+    1000:250:60:15 per-second mix (times `scale`), continuous batching, mixed precision."""
+    import torch
+    from paper_1712_06758_amd.serve import build_gpu_server
+    from workloads import SERVE_LEVELS, SERVE_CORR_LEN, poisson_arrivals
+    levels = sorted(SERVE_LEVELS)
+    srv = build_gpu_server(levels, SERVE_CORR_LEN, "mixed")
+    srv.run([(0.0, n, 10 ** 6 + i) for i, n in enumerate(levels)])   # warm-up, not reported
+    srv.done.clear()
+    srv.queue_depth.clear()
+    rates = {n: SERVE_LEVELS[n] * scale for n in levels}
+    arrivals = poisson_arrivals(rates, seconds, seed=2)
+    rep = srv.run(arrivals, time_limit=seconds * 4 + 30, progress_every=2.0)
+    rep["rates_per_s"] = rates
+    rep["arrival_window_s"] = seconds
+    del srv
+    torch.cuda.empty_cache()
+    return rep
 
 
 def main():
@@ -106,6 +139,9 @@ def main():
     ap.add_argument("--no-mesh", action="store_true", help="skip the tet transfer (solve only)")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
                     help="time one precision only (profiling runs)")
+    ap.add_argument("--serve-seconds", type=float, default=4.0,
+                    help="length of the serving load run reported beside the throughput (0: skip)")
+    ap.add_argument("--serve-scale", type=float, default=0.5, help="request-rate multiplier of the serving run")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -164,15 +200,20 @@ def main():
             results[prec]["batch1_samples_per_s"] = float("nan")
             del box
             continue
-        # batch of one, same path
-        x1 = xi[:1].contiguous()
-        b1_steps = max(3, args.steps // 2)
-        dt1, it1, _ = time_steps(torch, box, x1, b1_steps, 1)
-        results[prec]["batch1_samples_per_s"] = 1.0 / dt1
-        log(f"{prec}: batch 1: {1.0 / dt1:.1f} samples/s")
         info = box.info()
         results[prec]["info"] = info
         del box
+        torch.cuda.empty_cache()
+        # one sample per call on a single-sample sampler (its own tiles), same path
+        box1 = P.Box(w.n, w.kappa, w.g, precision=prec, max_batch=1, device=dev)
+        if mesh is not None:
+            box1.set_mesh(*mesh)
+        x1 = xi[:1].contiguous()
+        b1_steps = max(3, args.steps // 2)
+        dt1, it1, _ = time_steps(torch, box1, x1, b1_steps, 1)
+        results[prec]["batch1_samples_per_s"] = 1.0 / dt1
+        log(f"{prec}: batch 1: {1.0 / dt1:.1f} samples/s, tiles {box1.info()['tiles']}")
+        del box1
         torch.cuda.empty_cache()
 
     traffic = None
@@ -222,9 +263,12 @@ def main():
                         for k, v in results[p]["report"].items()} for p in results},
         "setup": setup,
     }
+    if args.serve_seconds > 0:
+        log(f"serving run: {args.serve_seconds} s at {args.serve_scale} x the request mix")
+        line["serving"] = serving_run(args.serve_seconds, args.serve_scale)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(w.n, w.kappa, w.g, xi_np, 4)
+        line["cpu_baseline"] = cpu_baseline(w.n, w.kappa, w.g, xi_np)
     print(json.dumps(line), flush=True)
 
 

@@ -235,8 +235,8 @@ spde_status spde_set_face_preconditioner(spde_handle h, int kind);
 /* Autotuning of the multigrid tile shapes (default on).  When on, the first
  * sample or V-cycle call of a handle times every admissible tile shape of each
  * per-level kernel at max_batch and keeps the fastest; the choice is shared by
- * all handles of the process with the same device architecture, n and
- * precision, and is appended to the file named by the environment variable
+ * all handles of the process with the same device architecture, n, precision
+ * and batch class of max_batch (1, 2..15, 16+), and is appended to the file named by the environment variable
  * SPDE_TUNE_CACHE (if set), from which later processes read it.  Off: fixed
  * default tiles.  Results depend on the tiles only through the rounding of
  * per-block partial sums (a few ulps). */

@@ -382,9 +382,10 @@ void close_timing(Ctx* c, int batch) {
 //
 // Chooses the tile shape of every per-level multigrid kernel by timing each
 // admissible shape at the context's largest batch.  The choice is keyed by
-// (device architecture, n, precision) only -- not by batch -- so that every
-// batch size of a context uses the same tiles, and the per-block partial sums
-// (hence the results) do not depend on how many samples share a launch.
+// (device architecture, n, precision, batch class of max_batch: 1, 2-15, 16+),
+// never by the batch of a call, so that every call of a context uses the same
+// tiles and the per-block partial sums (hence the results) do not depend on
+// how many samples share a launch.
 // Choices are kept for the process and, if SPDE_TUNE_CACHE names a file,
 // appended there as lines "key level down up".
 
@@ -399,8 +400,10 @@ std::string tune_key(Ctx* c) {
   if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
   const size_t cut = arch.find(':');
   if (cut != std::string::npos) arch = arch.substr(0, cut);
+  // batch class of the context's largest batch: 1, 2..15, 16+
+  const char* cls = c->max_batch == 1 ? "b1" : (c->max_batch < 16 ? "b2" : "b16");
   char buf[128];
-  snprintf(buf, sizeof buf, "%s:n%d:%s", arch.c_str(), c->n, c->fp64() ? "fp64" : "mixed");
+  snprintf(buf, sizeof buf, "%s:n%d:%s:%s", arch.c_str(), c->n, c->fp64() ? "fp64" : "mixed", cls);
   return buf;
 }
 

@@ -240,3 +240,27 @@ def test_face_preconditioners(torch_cuda, prec, bar):
         say(f"  kind {kind}: iters {out['iters'].tolist()} max err {err:.2e}")
         assert err <= bar
     assert iters[1] < iters[0]
+
+
+def test_edge_cases(torch_cuda):
+    """Smallest box, ragged batch against a larger max_batch, batch above max_batch."""
+    torch = torch_cuda
+    import paper_1712_06758_amd as PP
+    say("edge cases n=4, ragged batch, batch > max_batch")
+    n, kappa = 4, 3.0
+    box = PP.Box(n, kappa, precision="fp64", max_batch=5)
+    xi = xi_batch(n, [7, 8, 9])
+    out = box.sample(torch.tensor(xi, device="cuda"), u_box=True, sigma=True, relres=True)
+    ref = oracle_u(n, kappa, gval(kappa), xi)
+    u = out["u_box"].cpu().numpy()
+    assert max(rel_l2(u[b], ref[b]) for b in range(3)) <= 1e-10
+    assert max(out["relres"]) <= 1e-9
+    with pytest.raises(PP.SpdeError) as ei:
+        box.sample(torch.tensor(xi_batch(n, range(6)), device="cuda"))
+    assert ei.value.status == -2
+    # a 32^3 box with 7 samples (a batch that fills no power of two)
+    box = PP.Box(32, 20.0, precision="mixed", max_batch=7)
+    xi = xi_batch(32, range(20, 27))
+    u = box.sample(torch.tensor(xi, device="cuda"), u_box=True)["u_box"].cpu().numpy()
+    ref = oracle_u(32, 20.0, gval(20.0), xi)
+    assert max(rel_l2(u[b], ref[b]) for b in range(7)) <= 1e-7
