@@ -237,7 +237,8 @@ spde_status spde_set_face_preconditioner(spde_handle h, int kind);
  * per-level kernel at max_batch and keeps the fastest; the choice is shared by
  * all handles of the process with the same device architecture, n, precision
  * and batch class of max_batch (1, 2..15, 16+), and is appended to the file named by the environment variable
- * SPDE_TUNE_CACHE (if set), from which later processes read it.  Off: fixed
+ * SPDE_TUNE_CACHE (if set), from which later processes read it; with
+ * SPDE_TUNE_VERBOSE=1 every timed shape is printed to stderr.  Off: fixed
  * default tiles.  Results depend on the tiles only through the rounding of
  * per-block partial sums (a few ulps). */
 spde_status spde_set_autotune(spde_handle h, int enable);
@@ -246,6 +247,7 @@ spde_status spde_set_autotune(spde_handle h, int enable);
  *   3-D tiles (x*y*z cells):   0: 16x8x8  1: 8x8x8  2: 32x8x4  3: 16x16x4
  *                              4: 32x4x4  5: 16x8x4  (float64 up-kernels: 1, 4, 5 only)
  *   2.5-D columns x planes:    6: 32x8 x 32  7: 16x16 x 32  8: 32x8 x 16  9: 32x8 x 64
+ *   pipelined 2.5-D columns:  10: 32x8 x 32 11: 16x16 x 32 12: 32x8 x 64 13: 16x16 x 64
  * spde_set_tiles fixes the shapes of one level (or all levels with level = -1)
  * and turns autotuning off for the handle; spde_get_tiles reads them. */
 spde_status spde_set_tiles(spde_handle h, int level, int down_shape, int up_shape);

@@ -472,6 +472,8 @@ spde_status autotune(Ctx* c, hipStream_t st) {
       HIPCHK(hipMemsetAsync(c->mge[l], 0, (size_t)B * c->lv[l].nc * c->szm(), st));
     }
     std::vector<std::pair<int, int>> v(c->top, {0, f64 ? 1 : 0});
+    const char* verbose = getenv("SPDE_TUNE_VERBOSE");
+    const bool say = verbose && *verbose && *verbose != '0';
     for (int l = 0; l < c->top; ++l) {
       const bool fine = l == 0;
       const void* bsrc = fine ? (const void*)c->F.vu[0] : c->mgb[l];
@@ -484,6 +486,7 @@ spde_status autotune(Ctx* c, hipStream_t st) {
           return launch_mg_down(f64, sh, fine, bsrc, bsrc, c->mgb[l + 1], c->lv[l], B, nullptr, st);
         }, &ms);
         if (s != SPDE_OK) return s;
+        if (say) fprintf(stderr, "spde autotune %s level %d down shape %2d: %.4f ms\n", key.c_str(), l, sh, ms);
         if (ms < best) { best = ms; v[l].first = sh; }
       }
       best = 1e30f;
@@ -495,6 +498,7 @@ spde_status autotune(Ctx* c, hipStream_t st) {
                               c->F.vs[0], c->F.vs[0], fine ? c->F.part_up : nullptr, c->box, st);
         }, &ms);
         if (s != SPDE_OK) return s;
+        if (say) fprintf(stderr, "spde autotune %s level %d up shape %2d: %.4f ms\n", key.c_str(), l, sh, ms);
         if (ms < best) { best = ms; v[l].second = sh; }
       }
     }
@@ -873,7 +877,8 @@ spde_status spde_apply_vcycle(spde_handle h, int batch, const double* r_dev, dou
   void* out = c->fp64() ? (void*)z_dev : c->F.z[0];
   s = autotune(c, st);
   if (s != SPDE_OK) return s;
-  s = enqueue_vcycle(c, batch, st, 0, r_dev, r_dev, out, out, nullptr, nullptr);
+  // the finest up kernel always writes partial sums: give it the solver's buffer
+  s = enqueue_vcycle(c, batch, st, 0, r_dev, r_dev, out, out, nullptr, c->F.part_up);
   if (s != SPDE_OK) return s;
   if (!c->fp64()) HIPCHK(launch_f32_to_f64((const float*)c->F.z[0], z_dev, (int64_t)batch * c->box.nc, st));
   return SPDE_OK;

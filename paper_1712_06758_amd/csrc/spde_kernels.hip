@@ -1342,4 +1342,5 @@ __global__ __launch_bounds__(kBlock) void k_convert(const TS* __restrict__ s, TD
 
 }  // namespace spde
 
+#include "spde_vcycle.inc"
 #include "spde_launch.inc"
