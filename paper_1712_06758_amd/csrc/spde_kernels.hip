@@ -1022,7 +1022,47 @@ __global__ __launch_bounds__(kBlock) void k_scalar(Fields F, int nb_up, int nb_p
 //   (B^T z_u)_face = h^2 (zhat[c - e_d] - zhat[c]) / gamma
 //   (A z)_cell = (h^2 q sum_d (z_hi - z_lo) / q - kappa^2 h^3 zhat) / gamma
 
-template <typename TZ>
+// Face window along one grid line extended by odd reflection about the
+// boundary faces 0 and n (v_{-g} = -v_g, v_n = 0): w[k + 3] = v_{idx + k},
+// k = -R..R, zero outside the radius.  Every load is issued unconditionally
+// from an address on the line; the reflection makes the interior stencils of
+// line_terms_ext exact next to the boundary as well.
+template <int R>
+__device__ __forceinline__ void line_load_ext(const double* __restrict__ v, int64_t c, int64_t stride, int idx,
+                                              int n, double* w) {
+#pragma unroll
+  for (int k = -3; k <= 3; ++k) {
+    if (k < -R || k > R) {
+      w[k + 3] = 0.0;
+      continue;
+    }
+    const int g = idx + k;
+    const bool neg = g < 0 || g > n;
+    const int src = g < 0 ? -g : (g > n ? 2 * n - g : g);
+    const double x = v[c + (int64_t)(min(src, n - 1) - idx) * stride];
+    // a factor, not a select: a select lets the compiler move the load into a
+    // branch and wait for it there
+    w[k + 3] = x * (src == n ? 0.0 : (neg ? -1.0 : 1.0));
+  }
+}
+
+// line_terms on a reflected window (no boundary cases).
+__device__ __forceinline__ void line_terms_ext(const double* w, int poly, double& mz, double& zf, double& zh) {
+  if (poly) {
+    const double a = w[2] + w[4];
+    zf = 1.125 * w[3] - 0.25 * a + 0.0625 * (w[1] + w[5]);
+    zh = 1.125 * w[4] - 0.25 * (w[3] + w[5]) + 0.0625 * (w[2] + w[6]);
+    mz = w[3] + 0.015625 * ((w[0] + w[6]) + 3.0 * a);
+  } else {
+    mz = w[3] + 0.25 * (w[2] + w[4]);
+    zf = w[3];
+    zh = w[4];
+  }
+}
+
+// UNI: every wave lies in one grid row (n >= 64), so the y and z line
+// positions, and with them the y- and z-window offsets, are wave-uniform.
+template <typename TZ, bool UNI>
 __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int slot = lb / nb, blk = lb - slot * nb;
@@ -1036,57 +1076,73 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
   const int64_t n2 = bx.n2;
   const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
   if (c >= nc) return;
-  const int i = (int)(c % n), jj = (int)((c / n) % n), k = (int)(c / n2);
+  const int i = (int)(c % n);
+  int jj = (int)((c / n) % n), k = (int)(c / n2);
+  if constexpr (UNI) {
+    jj = __builtin_amdgcn_readfirstlane(jj);
+    k = __builtin_amdgcn_readfirstlane(k);
+  }
   const int64_t co = cell_off(slot, nc);
-  if (state == ST_ACTIVE) {
-    const double zs = S->zs, av = S->a_v, bv = S->b_v;
-    const bool has_prev = j > 1;
-    const TZ* z = reinterpret_cast<const TZ*>(F.z[p]) + co;
-    const double zc = (double)z[c];
-    const int idx[3] = {i, jj, k};
-    const int64_t str[3] = {1, n, n2};
-    double dv = 0.0;
-    double nf[3];
+  const bool active = state == ST_ACTIVE;
+  const bool has_prev = j > 1;
+  const int wm = S->wmode;
+  // x is written on even iterations and on the finishing pass; an odd
+  // iteration leaves its term to the next pass (coefficient xpend of w_{j-1})
+  const bool upd_x = wm >= 0 && ((j & 1) == 0 || state == ST_FINISH || wm == 0);
+  const int idx[3] = {i, jj, k};
+  const int64_t str[3] = {1, n, n2};
+  // scalars before any store (after a store they could no longer be scalar loads)
+  const double zs = S->zs, av = S->a_v, bv = S->b_v;
+  const double swz = S->wz, sww = S->ww, swwp = S->ww_prev, sxw = S->xw, sxp = S->xpend;
+
+  // All loads first, unconditionally (the addresses are valid in every state;
+  // values that a state does not need are discarded).  The stores go through
+  // pointers that may alias the loads, so a load after a store, or inside a
+  // branch the compiler may sink below the stores, would cost the wave another
+  // memory round trip.
+  const TZ* z = reinterpret_cast<const TZ*>(F.z[p]) + co;
+  double w[3][7], vo[3], zlo[3];
+  const double zc = (double)z[c];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    // radius 3 in either face-block mode (a branch here would split the
+    // loads into groups that each wait for their own data)
+    line_load_ext<3>(F.vs[p] + face_off(slot, d, nc), c, str[d], idx[d], n, w[d]);
+    zlo[d] = (double)z[idx[d] > 0 ? c - str[d] : c];
+    vo[d] = F.vs[pq][face_off(slot, d, nc) + c];
+  }
+  const double vuc = F.vu[p][co + c], vuo = F.vu[pq][co + c];
+  const double zp = (double)(reinterpret_cast<const TZ*>(F.z[pq]) + co)[c];
+  const double w1c = F.w[pq][co + c], wjc = F.w[p][co + c];
+
+  if (active) {
+    double dv = 0.0, nf[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const double* v = F.vs[p] + face_off(slot, d, nc);
-      double w[7], mz, zf, zh;
-      if (bx.poly) line_load<3>(v, c, str[d], idx[d], n, w);
-      else line_load<1>(v, c, str[d], idx[d], n, w);
-      line_terms(w, idx[d], n, bx.poly, mz, zf, zh);
+      double mz, zf, zh;
+      line_terms_ext(w[d], bx.poly, mz, zf, zh);
       dv += zh - zf;
-      double a = 0.0;
-      if (idx[d] > 0) a = zs * (mz + bx.h2 * ((double)z[c - str[d]] - zc));
-      double* o = F.vs[pq] + face_off(slot, d, nc);
-      double nv = a - av * w[3];
-      if (has_prev) nv -= bv * o[c];
-      nf[d] = idx[d] > 0 ? nv : 0.0;
+      const double a = zs * (mz + bx.h2 * (zlo[d] - zc));
+      const double nv = a - av * w[d][3];
+      nf[d] = idx[d] > 0 ? (has_prev ? nv - bv * vo[d] : nv) : 0.0;
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) F.vs[pq][face_off(slot, d, nc) + c] = nf[d];
     const double Au = zs * (bx.h2q * dv - bx.k2h3 * zc);
-    double* ou = F.vu[pq] + co;
-    double nu = Au - av * F.vu[p][co + c];
-    if (has_prev) nu -= bv * ou[c];
-    ou[c] = nu;
+    const double nu = Au - av * vuc;
+    F.vu[pq][co + c] = has_prev ? nu - bv * vuo : nu;
   }
-  const int wm = S->wmode;
-  if (wm >= 0) {
-    // w_j = wz zhat_{j-1} + ww_prev w_{j-2} + ww w_{j-1};  x_{j-1} = x_{j-2} + xw w_j
-    const TZ* zp = reinterpret_cast<const TZ*>(F.z[pq]) + co;
-    double* wj = F.w[p] + co;          // holds w_{j-2}, receives w_j
-    const double* w1 = F.w[pq] + co;   // w_{j-1}
-    double w1c = 0.0;
-    double wn = S->wz * (double)zp[c];
-    if (wm >= 1) { w1c = w1[c]; wn += S->ww * w1c; }
-    if (wm >= 2) wn += S->ww_prev * wj[c];
-    wj[c] = wn;
-    // x is written on even iterations and on the finishing pass; an odd
-    // iteration leaves its term to the next pass (coefficient xpend of w_{j-1})
-    if ((j & 1) == 0 || state == ST_FINISH || wm == 0) {
-      double* x = F.x + co;
-      const double inc = S->xpend * w1c + S->xw * wn;
-      x[c] = (wm == 0) ? inc : x[c] + inc;
+  {
+    // w_j = wz zhat_{j-1} + ww_prev w_{j-2} + ww w_{j-1};  x_{j-1} = x_{j-2} + xw w_j.
+    // The store is unconditional (a pass without w update writes back the old
+    // value) so that the loads above stay where they are.
+    double wn = swz * zp;
+    if (wm >= 1) wn += sww * w1c;
+    if (wm >= 2) wn += swwp * wjc;
+    F.w[p][co + c] = wm >= 0 ? wn : wjc;
+    if (upd_x) {
+      const double inc = sxp * (wm >= 1 ? w1c : 0.0) + sxw * wn;
+      F.x[co + c] = wm == 0 ? inc : F.x[co + c] + inc;
     }
   }
 }
