@@ -224,6 +224,14 @@ spde_status spde_apply_transfer(spde_handle h, int batch, const double* u_box_de
  * kernels one by one (0).  Results are bitwise identical either way. */
 spde_status spde_set_graphs(spde_handle h, int enable);
 
+/* Streams per spde_sample call: 2 runs a batch of 8 or more as two halves,
+ * the second on a stream of the library's own, so that the kernels of one half
+ * overlap those of the other; 1 (default) runs the batch as one.  The halves
+ * meet at every convergence poll and the call returns when both are done; the
+ * caller's stream sees the whole call as ordered work.  Results are bitwise
+ * identical either way.  EINVAL for other values. */
+spde_status spde_set_split(spde_handle h, int ways);
+
 /* Face (flux) block of the MINRES preconditioner: 0 = diag(M)^-1;
  * 1 (default) = the truncated Neumann series q (I - S + S^2) of M^-1 along each
  * grid line (M = (1/q)(I + S) on a line, q = 3/(2h^3)).  Both are symmetric

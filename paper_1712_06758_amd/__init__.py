@@ -64,7 +64,8 @@ class _Handle:
         self.h = h
 
     def __del__(self):
-        if getattr(self, "h", None) and _abi._lib is not None:
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "h", None) and _abi is not None and getattr(_abi, "_lib", None) is not None:
             _abi._lib.spde_destroy(self.h)
             self.h = None
 
@@ -242,6 +243,10 @@ class Box:
     # -- execution options / instrumentation ------------------------------
     def set_graphs(self, enable: bool):
         _abi.check(_abi.lib().spde_set_graphs(self._hh.h, int(bool(enable))))
+
+    def set_split(self, ways: int):
+        """Run batches of 8+ as two halves on two streams (2) or as one (1, default)."""
+        _abi.check(_abi.lib().spde_set_split(self._hh.h, int(ways)))
 
     def set_poll_interval(self, k: int):
         _abi.check(_abi.lib().spde_set_poll_interval(self._hh.h, int(k)))

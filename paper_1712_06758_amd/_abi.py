@@ -37,6 +37,7 @@ SIGNATURES = {
     "spde_apply_vcycle": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "spde_apply_transfer": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "spde_set_graphs": (C.c_int, [_vp, C.c_int]),
+    "spde_set_split": (C.c_int, [_vp, C.c_int]),
     "spde_set_poll_interval": (C.c_int, [_vp, C.c_int]),
     "spde_set_autotune": (C.c_int, [_vp, C.c_int]),
     "spde_set_face_preconditioner": (C.c_int, [_vp, C.c_int]),

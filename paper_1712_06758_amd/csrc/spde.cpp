@@ -63,6 +63,7 @@ struct LaunchRec {
   int kid;
   int iter;          // MINRES iteration of the launch (0 outside the loop)
   int level;         // multigrid level of a level kernel
+  int s0, nslots;    // slots of the launch (nslots < 0: the whole batch)
   hipEvent_t e0, e1;
 };
 
@@ -96,6 +97,8 @@ struct Ctx {
   void* mge[kMaxLevels] = {};   // level corrections (l >= 1)
   double* resid_out = nullptr;  // [max_batch]
   hipStream_t own_stream = nullptr;
+  hipStream_t aux_stream = nullptr;   // second half of a split batch
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   Scalars* host_sc = nullptr;   // pinned
   double* host_res = nullptr;   // pinned
   // transfer
@@ -107,7 +110,8 @@ struct Ctx {
   // execution
   bool use_graphs = true;
   int poll = 8;
-  std::map<int, hipGraphExec_t> graphs;   // batch -> K-iteration graph
+  std::map<int64_t, hipGraphExec_t> graphs;   // (first slot, batch) -> K-iteration graph
+  int split = 1;                 // 2: batches of 8+ run as two halves on two streams
   bool tuned = false;
   bool autotune = true;
   int face_precond = 1;          // 0 diag(M)^-1, 1 truncated Neumann series of M^-1
@@ -218,11 +222,11 @@ hipEvent_t next_event(Ctx* c) {
 
 struct Timed {
   Ctx* c;
-  int kid, iter, level;
+  int kid, iter, level, s0, nslots;
   hipStream_t st;
   hipEvent_t e0 = nullptr;
-  Timed(Ctx* c_, int kid_, int iter_, hipStream_t st_, int level_ = 0)
-      : c(c_), kid(kid_), iter(iter_), level(level_), st(st_) {
+  Timed(Ctx* c_, int kid_, int iter_, hipStream_t st_, int level_ = 0, int s0_ = 0, int nslots_ = -1)
+      : c(c_), kid(kid_), iter(iter_), level(level_), s0(s0_), nslots(nslots_), st(st_) {
     if (c->timing) {
       e0 = next_event(c);
       if (e0) hipEventRecord(e0, st);
@@ -233,7 +237,7 @@ struct Timed {
       hipEvent_t e1 = next_event(c);
       if (e1) {
         hipEventRecord(e1, st);
-        c->recs.push_back({kid, iter, level, e0, e1});
+        c->recs.push_back({kid, iter, level, s0, nslots, e0, e1});
       }
     }
   }
@@ -268,56 +272,90 @@ double slot_bytes(const Ctx* c, int kid, int level, int iter, int wmode_active) 
 
 // ---- one MINRES iteration (all kernels), enqueued on st ------------------------
 
-spde_status enqueue_vcycle(Ctx* c, int batch, hipStream_t st, int iter, const void* b0, const void* b1,
-                           void* o0, void* o1, const Scalars* sc, double* part) {
+// The slots [s0, s0 + batch) of the context: device pointers advanced to slot
+// s0, so that every kernel sees its sub-batch as slots 0 .. batch-1.
+struct View {
+  int s0 = 0;
+  Fields F{};
+  void* mgb[kMaxLevels] = {};
+  void* mge[kMaxLevels] = {};
+};
+
+View make_view(const Ctx* c, int s0) {
+  View V;
+  V.s0 = s0;
+  V.F = c->F;
+  const int64_t nc = c->box.nc;
+  const size_t sz = c->szm();
+  for (int p = 0; p < 2; ++p) {
+    V.F.vs[p] += (int64_t)s0 * 3 * nc;
+    V.F.vu[p] += (int64_t)s0 * nc;
+    V.F.z[p] = (char*)c->F.z[p] + (size_t)s0 * nc * sz;
+    V.F.w[p] += (int64_t)s0 * nc;
+  }
+  V.F.x += (int64_t)s0 * nc;
+  V.F.part_up += (int64_t)s0 * tiles_for(c->shape_up[0], c->n) * 2;
+  V.F.part_pb += (int64_t)s0 * c->nb_pb;
+  V.F.sc += s0;
+  for (int l = 1; l < c->nlev; ++l) {
+    if (c->mgb[l]) V.mgb[l] = (char*)c->mgb[l] + (size_t)s0 * c->lv[l].nc * sz;
+    if (c->mge[l]) V.mge[l] = (char*)c->mge[l] + (size_t)s0 * c->lv[l].nc * sz;
+  }
+  return V;
+}
+
+spde_status enqueue_vcycle(Ctx* c, const View& V, int batch, hipStream_t st, int iter, const void* b0,
+                           const void* b1, void* o0, void* o1, const Scalars* sc, double* part) {
   const bool f64 = c->fp64();
+  const int s0 = V.s0;
   {
-    Timed t(c, KID_MG_DOWN_FINE, iter, st);
-    HIPCHK(launch_mg_down(f64, c->shape_down[0], true, b0, b1, c->mgb[1], c->lv[0], batch, sc, st));
+    Timed t(c, KID_MG_DOWN_FINE, iter, st, 0, s0, batch);
+    HIPCHK(launch_mg_down(f64, c->shape_down[0], true, b0, b1, V.mgb[1], c->lv[0], batch, sc, st));
   }
   for (int l = 1; l < c->top; ++l) {
-    Timed t(c, KID_MG_DOWN, iter, st, l);
-    HIPCHK(launch_mg_down(f64, c->shape_down[l], false, c->mgb[l], c->mgb[l], c->mgb[l + 1], c->lv[l], batch, sc, st));
+    Timed t(c, KID_MG_DOWN, iter, st, l, s0, batch);
+    HIPCHK(launch_mg_down(f64, c->shape_down[l], false, V.mgb[l], V.mgb[l], V.mgb[l + 1], c->lv[l], batch, sc, st));
   }
   {
-    Timed t(c, KID_MG_COARSE, iter, st);
-    HIPCHK(launch_mg_coarse(f64, c->mgb[c->top], c->mge[c->top], c->cp, c->coarse_lds, batch, sc, st));
+    Timed t(c, KID_MG_COARSE, iter, st, 0, s0, batch);
+    HIPCHK(launch_mg_coarse(f64, V.mgb[c->top], V.mge[c->top], c->cp, c->coarse_lds, batch, sc, st));
   }
   for (int l = c->top - 1; l >= 1; --l) {
-    Timed t(c, KID_MG_UP, iter, st, l);
-    HIPCHK(launch_mg_up(f64, c->shape_up[l], false, c->mgb[l], c->mgb[l], c->mge[l + 1], c->mge[l], c->mge[l],
+    Timed t(c, KID_MG_UP, iter, st, l, s0, batch);
+    HIPCHK(launch_mg_up(f64, c->shape_up[l], false, V.mgb[l], V.mgb[l], V.mge[l + 1], V.mge[l], V.mge[l],
                         c->lv[l], batch, sc, nullptr, nullptr, nullptr, c->box, st));
   }
   {
-    Timed t(c, KID_MG_UP_FINE, iter, st);
-    HIPCHK(launch_mg_up(f64, c->shape_up[0], true, b0, b1, c->mge[1], o0, o1, c->lv[0], batch, sc,
-                        c->F.vs[0], c->F.vs[1], part, c->box, st));
+    Timed t(c, KID_MG_UP_FINE, iter, st, 0, s0, batch);
+    HIPCHK(launch_mg_up(f64, c->shape_up[0], true, b0, b1, V.mge[1], o0, o1, c->lv[0], batch, sc,
+                        V.F.vs[0], V.F.vs[1], part, c->box, st));
   }
   return SPDE_OK;
 }
 
-spde_status enqueue_iteration(Ctx* c, int batch, hipStream_t st, int iter) {
-  spde_status s = enqueue_vcycle(c, batch, st, iter, c->F.vu[0], c->F.vu[1], c->F.z[0], c->F.z[1], c->F.sc,
-                                 c->F.part_up);
+spde_status enqueue_iteration(Ctx* c, const View& V, int batch, hipStream_t st, int iter) {
+  spde_status s = enqueue_vcycle(c, V, batch, st, iter, V.F.vu[0], V.F.vu[1], V.F.z[0], V.F.z[1], V.F.sc,
+                                 V.F.part_up);
   if (s != SPDE_OK) return s;
   {
-    Timed t(c, KID_SCALAR, iter, st);
-    HIPCHK(launch_scalar(c->F, tiles_for(c->shape_up[0], c->n), c->nb_pb, batch, st));
+    Timed t(c, KID_SCALAR, iter, st, 0, V.s0, batch);
+    HIPCHK(launch_scalar(V.F, tiles_for(c->shape_up[0], c->n), c->nb_pb, batch, st));
   }
   {
-    Timed t(c, KID_OPERATOR, iter, st);
-    HIPCHK(launch_operator(c->fp64(), c->F, c->box, batch, st));
+    Timed t(c, KID_OPERATOR, iter, st, 0, V.s0, batch);
+    HIPCHK(launch_operator(c->fp64(), V.F, c->box, batch, st));
   }
   return SPDE_OK;
 }
 
-spde_status get_graph(Ctx* c, int batch, hipStream_t st, hipGraphExec_t* out) {
-  auto it = c->graphs.find(batch);
+spde_status get_graph(Ctx* c, const View& V, int batch, hipStream_t st, hipGraphExec_t* out) {
+  const int64_t key = ((int64_t)V.s0 << 32) | (int64_t)batch;
+  auto it = c->graphs.find(key);
   if (it != c->graphs.end()) { *out = it->second; return SPDE_OK; }
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   spde_status s = SPDE_OK;
-  for (int k = 0; k < c->poll && s == SPDE_OK; ++k) s = enqueue_iteration(c, batch, st, 0);
+  for (int k = 0; k < c->poll && s == SPDE_OK; ++k) s = enqueue_iteration(c, V, batch, st, 0);
   hipError_t e = hipStreamEndCapture(st, &g);
   if (s != SPDE_OK) { if (g) hipGraphDestroy(g); return s; }
   if (e != hipSuccess) return fail(SPDE_EHIP, "graph capture: %s", hipGetErrorString(e));
@@ -325,8 +363,29 @@ spde_status get_graph(Ctx* c, int batch, hipStream_t st, hipGraphExec_t* out) {
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   if (e != hipSuccess) return fail(SPDE_EHIP, "graph instantiate: %s", hipGetErrorString(e));
-  c->graphs[batch] = ex;
+  c->graphs[key] = ex;
   *out = ex;
+  return SPDE_OK;
+}
+
+// One poll interval of iterations for the slots of V (a captured graph if
+// graphs are on, else plain launches).
+spde_status enqueue_block(Ctx* c, const View& V, int batch, hipStream_t st, bool graphs, int iter0) {
+  hipGraphExec_t ex = nullptr;
+  if (graphs && get_graph(c, V, batch, st, &ex) != SPDE_OK) {
+    // capture not available on this stream: fall back to plain launches
+    hipGetLastError();
+    c->use_graphs = false;
+    ex = nullptr;
+  }
+  if (ex) {
+    HIPCHK(hipGraphLaunch(ex, st));
+    return SPDE_OK;
+  }
+  for (int k = 0; k < c->poll; ++k) {
+    spde_status s = enqueue_iteration(c, V, batch, st, iter0 + k + 1);
+    if (s != SPDE_OK) return s;
+  }
   return SPDE_OK;
 }
 
@@ -357,7 +416,8 @@ void close_timing(Ctx* c, int batch) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) continue;
     double bytes = 0.0;
-    for (int s = 0; s < batch; ++s) {
+    const int s_end = r.nslots < 0 ? batch : std::min(batch, r.s0 + r.nslots);
+    for (int s = r.s0; s < s_end; ++s) {
       const bool done = states[s] == ST_DONE || states[s] == ST_FINISH;
       const int J = done ? iters[s] : (1 << 30);
       if (r.kid == KID_OPERATOR) {
@@ -588,11 +648,18 @@ spde_status spde_bind_workspace(spde_handle h, void* dev_ptr, size_t bytes) {
   HIPCHK(hipGetDevice(&dev));
   if (c->device != dev) {
     if (c->own_stream) { hipStreamDestroy(c->own_stream); c->own_stream = nullptr; }
+    if (c->aux_stream) { hipStreamDestroy(c->aux_stream); c->aux_stream = nullptr; }
+    if (c->ev_fork) { hipEventDestroy(c->ev_fork); c->ev_fork = nullptr; }
+    if (c->ev_join) { hipEventDestroy(c->ev_join); c->ev_join = nullptr; }
     c->device = dev;
     int lds = 65536;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
       c->lds_limit = lds;
     HIPCHK(hipStreamCreate(&c->own_stream));
+    // default priority, like every stream of the library
+    HIPCHK(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     if (!c->host_sc) HIPCHK(hipHostMalloc((void**)&c->host_sc, 4096 * sizeof(Scalars), hipHostMallocDefault));
     if (!c->host_res) HIPCHK(hipHostMalloc((void**)&c->host_res, 4096 * sizeof(double), hipHostMallocDefault));
   }
@@ -667,24 +734,28 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* 
     HIPCHK(launch_init(c->F, bx, xi_dev, scale, batch, c->rtol, c->max_iter, 0, st));
   }
   const bool graphs = c->use_graphs && !c->timing && st != nullptr;
+  // A batch of 8 or more runs as two halves on two streams, so that the
+  // memory-bound operator pass of one half can overlap the compute-bound
+  // V-cycle of the other and each fills the other's launch tails.  The halves
+  // are independent samples; they meet at every convergence poll.
+  const bool split = c->split >= 2 && batch >= 8 && c->aux_stream && st != nullptr;
+  const int b1 = split ? (batch + 1) / 2 : batch;
+  const View V0 = make_view(c, 0), V1 = make_view(c, b1);
+  if (split) {
+    HIPCHK(hipEventRecord(c->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0));
+  }
   int launched = 0;
   const int cap = c->max_iter + 2;
   bool all_done = false;
   while (!all_done && launched < cap + c->poll) {
-    hipGraphExec_t ex = nullptr;
-    if (graphs && get_graph(c, batch, st, &ex) != SPDE_OK) {
-      // capture not available on this stream: fall back to plain launches
-      hipGetLastError();
-      c->use_graphs = false;
-      ex = nullptr;
-    }
-    if (ex) {
-      HIPCHK(hipGraphLaunch(ex, st));
-    } else {
-      for (int k = 0; k < c->poll; ++k) {
-        s = enqueue_iteration(c, batch, st, launched + k + 1);
-        if (s != SPDE_OK) return s;
-      }
+    s = enqueue_block(c, V0, b1, st, graphs, launched);
+    if (s != SPDE_OK) return s;
+    if (split) {
+      s = enqueue_block(c, V1, batch - b1, c->aux_stream, graphs, launched);
+      if (s != SPDE_OK) return s;
+      HIPCHK(hipEventRecord(c->ev_join, c->aux_stream));
+      HIPCHK(hipStreamWaitEvent(st, c->ev_join, 0));
     }
     launched += c->poll;
     HIPCHK(hipMemcpyAsync(c->host_sc, c->F.sc, batch * sizeof(Scalars), hipMemcpyDeviceToHost, st));
@@ -770,9 +841,10 @@ spde_status spde_slots_step(spde_handle h, int nslots, int iters, void* stream) 
   hipStream_t st = pick_stream(c, stream);
   const bool graphs = c->use_graphs && !c->timing && st != nullptr;
   int done = 0;
+  const View V0 = make_view(c, 0);
   while (done < iters) {
     hipGraphExec_t ex = nullptr;
-    if (graphs && iters - done >= c->poll && get_graph(c, nslots, st, &ex) != SPDE_OK) {
+    if (graphs && iters - done >= c->poll && get_graph(c, V0, nslots, st, &ex) != SPDE_OK) {
       hipGetLastError();
       c->use_graphs = false;
       ex = nullptr;
@@ -781,7 +853,7 @@ spde_status spde_slots_step(spde_handle h, int nslots, int iters, void* stream) 
       HIPCHK(hipGraphLaunch(ex, st));
       done += c->poll;
     } else {
-      s = enqueue_iteration(c, nslots, st, 0);
+      s = enqueue_iteration(c, V0, nslots, st, 0);
       if (s != SPDE_OK) return s;
       done += 1;
     }
@@ -878,7 +950,7 @@ spde_status spde_apply_vcycle(spde_handle h, int batch, const double* r_dev, dou
   s = autotune(c, st);
   if (s != SPDE_OK) return s;
   // the finest up kernel always writes partial sums: give it the solver's buffer
-  s = enqueue_vcycle(c, batch, st, 0, r_dev, r_dev, out, out, nullptr, c->F.part_up);
+  s = enqueue_vcycle(c, make_view(c, 0), batch, st, 0, r_dev, r_dev, out, out, nullptr, c->F.part_up);
   if (s != SPDE_OK) return s;
   if (!c->fp64()) HIPCHK(launch_f32_to_f64((const float*)c->F.z[0], z_dev, (int64_t)batch * c->box.nc, st));
   return SPDE_OK;
@@ -913,6 +985,14 @@ spde_status spde_set_transfer_order(spde_handle h, const int32_t* order_dev) {
   if (!c) return fail(SPDE_EINVAL, "null handle");
   if (!c->rp) return fail(SPDE_EINVAL, "no transfer set");
   c->order = order_dev;
+  return SPDE_OK;
+}
+
+spde_status spde_set_split(spde_handle h, int ways) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (ways != 1 && ways != 2) return fail(SPDE_EINVAL, "split must be 1 or 2");
+  c->split = ways;
   return SPDE_OK;
 }
 
@@ -1022,6 +1102,9 @@ void spde_destroy(spde_handle h) {
   drop_graphs(c);
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->own_stream) hipStreamDestroy(c->own_stream);
+  if (c->aux_stream) hipStreamDestroy(c->aux_stream);
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
   if (c->host_sc) hipHostFree(c->host_sc);
   if (c->host_res) hipHostFree(c->host_res);
   delete c;

@@ -1062,7 +1062,9 @@ __device__ __forceinline__ void line_terms_ext(const double* w, int poly, double
 
 // UNI: every wave lies in one grid row (n >= 64), so the y and z line
 // positions, and with them the y- and z-window offsets, are wave-uniform.
-template <typename TZ, bool UNI>
+// POLY: face block of the preconditioner (0 diag(M)^-1, 1 Neumann series), a
+// template parameter so that no window load sits behind a branch on it.
+template <typename TZ, bool UNI, int POLY>
 __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int slot = lb / nb, blk = lb - slot * nb;
@@ -1095,6 +1097,24 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
   const double zs = S->zs, av = S->a_v, bv = S->b_v;
   const double swz = S->wz, sww = S->ww, swwp = S->ww_prev, sxw = S->xw, sxp = S->xpend;
 
+  // w_j = wz zhat_{j-1} + ww_prev w_{j-2} + ww w_{j-1};  x_{j-1} = x_{j-2} + xw w_j.
+  // The w store is unconditional (a pass without w update writes back the old
+  // value) so that the loads it needs stay ahead of the other stores.
+  auto wx_update = [&](double zp, double w1c, double wjc) {
+    double wn = swz * zp;
+    if (wm >= 1) wn += sww * w1c;
+    if (wm >= 2) wn += swwp * wjc;
+    F.w[p][co + c] = wm >= 0 ? wn : wjc;
+    if (upd_x) {
+      const double inc = sxp * (wm >= 1 ? w1c : 0.0) + sxw * wn;
+      F.x[co + c] = wm == 0 ? inc : F.x[co + c] + inc;
+    }
+  };
+  const TZ* zprev = reinterpret_cast<const TZ*>(F.z[pq]) + co;
+  if (!active) {   // the finishing pass only applies the last solution update
+    wx_update((double)zprev[c], F.w[pq][co + c], F.w[p][co + c]);
+    return;
+  }
   // All loads first, unconditionally (the addresses are valid in every state;
   // values that a state does not need are discarded).  The stores go through
   // pointers that may alias the loads, so a load after a store, or inside a
@@ -1112,39 +1132,25 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
     vo[d] = F.vs[pq][face_off(slot, d, nc) + c];
   }
   const double vuc = F.vu[p][co + c], vuo = F.vu[pq][co + c];
-  const double zp = (double)(reinterpret_cast<const TZ*>(F.z[pq]) + co)[c];
+  const double zp = (double)zprev[c];
   const double w1c = F.w[pq][co + c], wjc = F.w[p][co + c];
 
-  if (active) {
-    double dv = 0.0, nf[3];
+  double dv = 0.0, nf[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double mz, zf, zh;
-      line_terms_ext(w[d], bx.poly, mz, zf, zh);
-      dv += zh - zf;
-      const double a = zs * (mz + bx.h2 * (zlo[d] - zc));
-      const double nv = a - av * w[d][3];
-      nf[d] = idx[d] > 0 ? (has_prev ? nv - bv * vo[d] : nv) : 0.0;
-    }
+  for (int d = 0; d < 3; ++d) {
+    double mz, zf, zh;
+    line_terms_ext(w[d], POLY, mz, zf, zh);
+    dv += zh - zf;
+    const double a = zs * (mz + bx.h2 * (zlo[d] - zc));
+    const double nv = a - av * w[d][3];
+    nf[d] = idx[d] > 0 ? (has_prev ? nv - bv * vo[d] : nv) : 0.0;
+  }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) F.vs[pq][face_off(slot, d, nc) + c] = nf[d];
-    const double Au = zs * (bx.h2q * dv - bx.k2h3 * zc);
-    const double nu = Au - av * vuc;
-    F.vu[pq][co + c] = has_prev ? nu - bv * vuo : nu;
-  }
-  {
-    // w_j = wz zhat_{j-1} + ww_prev w_{j-2} + ww w_{j-1};  x_{j-1} = x_{j-2} + xw w_j.
-    // The store is unconditional (a pass without w update writes back the old
-    // value) so that the loads above stay where they are.
-    double wn = swz * zp;
-    if (wm >= 1) wn += sww * w1c;
-    if (wm >= 2) wn += swwp * wjc;
-    F.w[p][co + c] = wm >= 0 ? wn : wjc;
-    if (upd_x) {
-      const double inc = sxp * (wm >= 1 ? w1c : 0.0) + sxw * wn;
-      F.x[co + c] = wm == 0 ? inc : F.x[co + c] + inc;
-    }
-  }
+  for (int d = 0; d < 3; ++d) F.vs[pq][face_off(slot, d, nc) + c] = nf[d];
+  const double Au = zs * (bx.h2q * dv - bx.k2h3 * zc);
+  const double nu = Au - av * vuc;
+  F.vu[pq][co + c] = has_prev ? nu - bv * vuo : nu;
+  wx_update(zp, w1c, wjc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1285,13 +1291,20 @@ __global__ __launch_bounds__(kBlock) void k_resid_reduce(const double* __restric
 // ---------------------------------------------------------------------------
 // transfer: u_tet = Pi u (CSR, one thread per tet row, NR samples per pass)
 
+// One thread per row and NR samples per thread.  Blocks are numbered chunk
+// by chunk (the sample groups of a chunk of rows are consecutive) and mapped
+// XCD by XCD, so each XCD sweeps one range of rows: the rows' CSR entries are
+// fetched once, by the first of the chunk's group blocks, and the gathered
+// cells of the range stay in that XCD's cache.
 template <int NR>
 __global__ __launch_bounds__(kBlock) void k_spmm(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                  const double* __restrict__ cv, const double* __restrict__ u,
                                                  double* __restrict__ out, int64_t ntet, int64_t nnz, int64_t nc,
-                                                 int batch, const int32_t* __restrict__ order) {
-  const int64_t pos = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int s0 = blockIdx.y * NR;
+                                                 int batch, const int32_t* __restrict__ order, int ngroup) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int chunk = lb / ngroup, grp = lb - chunk * ngroup;
+  const int64_t pos = (int64_t)chunk * kBlock + threadIdx.x;
+  const int s0 = grp * NR;
   if (pos >= ntet) return;
   // rows are visited in `order` (if given) so that neighbouring threads gather
   // neighbouring cells; an out-of-range entry is skipped

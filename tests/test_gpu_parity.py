@@ -178,6 +178,26 @@ def test_restrict_noise_matches_oracle(torch_cuda):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_split_batch_matches_single_stream(torch_cuda, prec):
+    """A batch run as two halves on two streams gives bitwise the same fields,
+    iteration counts and tet values as the same batch on one stream."""
+    torch = torch_cuda
+    w = WORKLOADS["box64"]
+    say(f"split batch {prec} n=64 batch 9")
+    xi = torch.tensor(w.noise(9), device="cuda")
+    xyz, tets = w.mesh()
+    outs = []
+    for ways in (1, 2):
+        box = P().Box(w.n, w.kappa, precision=prec, max_batch=9)
+        box.set_mesh(xyz, tets)
+        box.set_split(ways)
+        outs.append(box.sample(xi, u_box=True))
+    assert np.array_equal(outs[0]["iters"], outs[1]["iters"])
+    assert torch.equal(outs[0]["u_box"], outs[1]["u_box"])
+    assert torch.equal(outs[0]["u_tet"], outs[1]["u_tet"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_every_tile_shape_gives_the_same_vcycle(torch_cuda, prec):
     """All tile shapes compute the same V-cycle up to summation order, and each
     is symmetric positive definite (MINRES needs an SPD preconditioner)."""
