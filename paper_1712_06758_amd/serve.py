@@ -370,7 +370,9 @@ def build_gpu_server(levels=(32, 64, 128, 256), corr_len=0.05, precision="mixed"
     g = g_unit_variance(kappa)
     levels = sorted(levels)
     sizes = sorted(set(levels) | {n // 2 for n in levels if n != levels[0]})
-    default_slots = {16: 32, 32: 64, 64: 48, 128: 16, 256: 4}
+    # small levels get many slots: a request then never waits for a free slot,
+    # and its latency is set by how fast its engine steps while sharing the GPU
+    default_slots = {16: 128, 32: 128, 64: 64, 128: 16, 256: 4}
     slots = slots or {n: default_slots.get(n, 8) for n in sizes}
     engines = {}
     meshes = {n: serve_mesh(n) for n in levels}
