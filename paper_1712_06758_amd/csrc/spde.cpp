@@ -249,15 +249,18 @@ double slot_bytes(const Ctx* c, int kid, int level, int iter, int wmode_active) 
   const double nc = (double)c->box.nc, sz = (double)c->szm();
   switch (kid) {
     case KID_OPERATOR: {
-      // v update: read v_j (faces 24, cell 8), v_{j-1} (32, from j = 2), zhat_j; write v_{j+1} (32)
-      // w/x update: read zhat_{j-1}, w_{j-1} (j >= 3), w_{j-2} (j >= 4); write w_j; x read+write on
-      // even passes and on the finishing pass, x write only at j = 2
+      // v update (iterations 1..J): read v_j (faces 24, cell 8), v_{j-1} (32, from j = 2), zhat_j;
+      // write v_{j+1} (32).  Direction update (iterations 1..J): read W_j (j >= 2) and W_{j-1}
+      // (j >= 3), write W_{j+1}.  x: written alone at j = 2, read and written on later even passes
+      // and on the finishing pass J + 1, which reads W_J and W_{J-1} and writes nothing else.
       double b = 0;
+      const bool fin = (wmode_active & 4) != 0;
       if (wmode_active & 1) b += nc * ((iter > 1 ? 64.0 : 32.0) + sz + 32.0);
-      if (wmode_active & 2) {
-        b += nc * (sz + 8.0 + (iter >= 3 ? 8.0 : 0.0) + (iter >= 4 ? 8.0 : 0.0));
+      if ((wmode_active & 2) && !fin) b += nc * (8.0 + (iter >= 2 ? 8.0 : 0.0) + (iter >= 3 ? 8.0 : 0.0));
+      if (fin) b += nc * (8.0 + (iter >= 4 ? 8.0 : 0.0));
+      if ((wmode_active & 2) && iter >= 2) {
         if (iter == 2) b += nc * 8.0;
-        else if ((iter % 2) == 0 || (wmode_active & 4)) b += nc * 16.0;
+        else if ((iter % 2) == 0 || fin) b += nc * 16.0;
       }
       return b;
     }
@@ -423,7 +426,7 @@ void close_timing(Ctx* c, int batch) {
       if (r.kid == KID_OPERATOR) {
         int mode = 0;
         if (r.iter <= J) mode |= 1;
-        if (r.iter >= 2 && r.iter <= J + 1) mode |= 2;
+        if (r.iter >= 1 && r.iter <= J + 1) mode |= 2;
         if (r.iter == J + 1) mode |= 4;
         bytes += slot_bytes(c, r.kid, 0, r.iter, mode);
       } else if (r.iter >= 1 && r.iter <= J + 1) {

@@ -43,15 +43,20 @@ struct alignas(16) Scalars {
   double zs;                  // 1 / gamma_j
   double a_v;                 // delta_j / gamma_j
   double b_v;                 // gamma_j / gamma_{j-1}
-  double wz, ww_prev, ww;     // w_j = wz zhat_{j-1} + ww_prev w_{j-2} + ww w_{j-1}
-  double xw;                  // x_{j-1} = x_{j-2} + xw w_j
-  double xpend;               // coefficient of w_{j-1} whose x update was deferred (0 if none)
+  // Directions are stored unnormalised, W_{j+1} = alpha1_j w_{j+1}, so that the
+  // operator pass of iteration j can form W_{j+1} from zhat_j before alpha1_j
+  // (which needs gamma_{j+1}) is known:
+  //   W_{j+1} = zs zhat_j + ww W_j + ww_prev W_{j-1};  x += xw W_j (+ xpend W_{j-1})
+  double ww, ww_prev;
+  double xw;                  // coefficient of W_j in the solution update
+  double xpend;               // coefficient of W_{j-1} whose x update was deferred (0 if none)
+  double al1_prev;            // alpha1 of the previous Givens step
   double tol;                 // relative stopping tolerance on |eta| / eta0
   int it;                     // iteration the V-cycle and the scalar step work on
   int pit;                    // iteration the operator pass works on
   int state;
   int flags;
-  int wmode;                  // -1 no w/x update, 0 first (no reads), 1 no w_{j-2}, 2 full
+  int wmode;                  // -1 no w/x update, 0 first (no reads), 1 no W_{j-1}, 2 full
   int iters;                  // iterations when finished
   int max_iter;
   int pad;

@@ -974,28 +974,34 @@ __global__ __launch_bounds__(kBlock) void k_scalar(Fields F, int nb_up, int nb_p
   if (j == 1) {
     s.eta = gam; s.eta0 = gam;
     s.c = s.c_prev = 1.0; s.s = s.s_prev = 0.0;
-    s.wmode = -1;
+    s.wmode = 0;                       // W_2 = z_1
+    s.ww = s.ww_prev = 0.0;
+    s.xw = s.xpend = 0.0;
+    s.al1_prev = 1.0;
     s.b_v = 0.0;
   } else {
     // complete the Givens rotation of step j-1 now that gamma_j is known
     const double dp = s.delta, gp = s.gamma;
     const double al0 = s.c * dp - s.c_prev * s.s * gp;
     const double al1 = sqrt(al0 * al0 + gg);
-    const double al2 = s.s * dp + s.c_prev * s.c * gp;
-    const double al3 = s.s_prev * gp;
     if (!(al1 > 0.0) || !isfinite(al1)) { s.state = ST_FAILED; s.iters = j - 1; *S = s; return; }
     const double cn = al0 / al1, sn = gam / al1;
-    s.wz = 1.0 / (al1 * gp);
-    s.ww_prev = -al3 / al1;
-    s.ww = -al2 / al1;
-    // the operator pass of an odd iteration >= 3 defers its solution update to
-    // the next pass (x absorbs two directions every other iteration)
+    // x_{j-1} = x_{j-2} + c_j eta w_j with w_j = W_j / alpha1_{j-1}.  The
+    // operator pass of an odd iteration >= 3 defers its solution update to the
+    // next pass (x absorbs two directions every other iteration).
     s.xpend = ((j - 1) % 2 == 1 && j - 1 >= 3) ? s.xw : 0.0;
-    s.xw = cn * s.eta;
+    s.xw = cn * s.eta / al1;
     s.eta = -sn * s.eta;
+    // W_{j+1} = z_j - alpha3_j w_{j-1} - alpha2_j w_j, with
+    // alpha2_j = s_j delta_j + c_{j-1} c_j gamma_j and alpha3_j = s_{j-1} gamma_j
+    const double a2 = sn * del + s.c * cn * gam;
+    const double a3 = s.s * gam;
+    s.ww = -a2 / al1;
+    s.ww_prev = -a3 / s.al1_prev;
+    s.al1_prev = al1;
     s.c_prev = s.c; s.s_prev = s.s;
     s.c = cn; s.s = sn;
-    s.wmode = (j == 2) ? 0 : ((j == 3) ? 1 : 2);
+    s.wmode = (j == 2) ? 1 : 2;
     s.b_v = gam / gp;
     if (fabs(s.eta) <= s.tol * s.eta0 || gg == 0.0) {
       s.state = ST_FINISH; s.iters = j - 1;
@@ -1089,30 +1095,27 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
   const bool has_prev = j > 1;
   const int wm = S->wmode;
   // x is written on even iterations and on the finishing pass; an odd
-  // iteration leaves its term to the next pass (coefficient xpend of w_{j-1})
-  const bool upd_x = wm >= 0 && ((j & 1) == 0 || state == ST_FINISH || wm == 0);
+  // iteration leaves its term to the next pass (coefficient xpend of W_{j-1})
+  const bool upd_x = wm >= 1 && ((j & 1) == 0 || state == ST_FINISH);
   const int idx[3] = {i, jj, k};
   const int64_t str[3] = {1, n, n2};
   // scalars before any store (after a store they could no longer be scalar loads)
   const double zs = S->zs, av = S->a_v, bv = S->b_v;
-  const double swz = S->wz, sww = S->ww, swwp = S->ww_prev, sxw = S->xw, sxp = S->xpend;
+  const double sww = S->ww, swwp = S->ww_prev, sxw = S->xw, sxp = S->xpend;
 
-  // w_j = wz zhat_{j-1} + ww_prev w_{j-2} + ww w_{j-1};  x_{j-1} = x_{j-2} + xw w_j.
-  // The w store is unconditional (a pass without w update writes back the old
+  // Direction and solution updates (unnormalised directions, see Scalars):
+  //   W_{j+1} = zs zhat_j + ww W_j + ww_prev W_{j-1}      (W_j in w[pq], W_{j-1} in w[p])
+  //   x += xpend W_{j-1} + xw W_j                          (even passes, the finishing pass)
+  // The W store is unconditional (a pass without update writes back the old
   // value) so that the loads it needs stay ahead of the other stores.
-  auto wx_update = [&](double zp, double w1c, double wjc) {
-    double wn = swz * zp;
-    if (wm >= 1) wn += sww * w1c;
-    if (wm >= 2) wn += swwp * wjc;
-    F.w[p][co + c] = wm >= 0 ? wn : wjc;
+  auto x_update = [&](double wj, double wjm1) {
     if (upd_x) {
-      const double inc = sxp * (wm >= 1 ? w1c : 0.0) + sxw * wn;
-      F.x[co + c] = wm == 0 ? inc : F.x[co + c] + inc;
+      const double inc = sxp * wjm1 + sxw * wj;
+      F.x[co + c] = j == 2 ? inc : F.x[co + c] + inc;
     }
   };
-  const TZ* zprev = reinterpret_cast<const TZ*>(F.z[pq]) + co;
   if (!active) {   // the finishing pass only applies the last solution update
-    wx_update((double)zprev[c], F.w[pq][co + c], F.w[p][co + c]);
+    x_update(F.w[pq][co + c], wm >= 2 ? F.w[p][co + c] : 0.0);
     return;
   }
   // All loads first, unconditionally (the addresses are valid in every state;
@@ -1132,8 +1135,7 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
     vo[d] = F.vs[pq][face_off(slot, d, nc) + c];
   }
   const double vuc = F.vu[p][co + c], vuo = F.vu[pq][co + c];
-  const double zp = (double)zprev[c];
-  const double w1c = F.w[pq][co + c], wjc = F.w[p][co + c];
+  const double wj = F.w[pq][co + c], wjm1 = F.w[p][co + c];
 
   double dv = 0.0, nf[3];
 #pragma unroll
@@ -1150,7 +1152,11 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
   const double Au = zs * (bx.h2q * dv - bx.k2h3 * zc);
   const double nu = Au - av * vuc;
   F.vu[pq][co + c] = has_prev ? nu - bv * vuo : nu;
-  wx_update(zp, w1c, wjc);
+  double wn = zs * zc;
+  if (wm >= 1) wn += sww * wj;
+  if (wm >= 2) wn += swwp * wjm1;
+  F.w[p][co + c] = wm >= 0 ? wn : wjm1;
+  if (wm >= 1) x_update(wj, wm >= 2 ? wjm1 : 0.0);
 }
 
 // ---------------------------------------------------------------------------
