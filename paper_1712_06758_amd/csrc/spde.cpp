@@ -112,6 +112,7 @@ struct Ctx {
   int poll = 8;
   std::map<int64_t, hipGraphExec_t> graphs;   // (first slot, batch) -> K-iteration graph
   int split = 1;                 // 2: batches of 8+ run as two halves on two streams
+  int expect_iters = 0;          // iterations (incl. the finishing pass) the last call needed
   bool tuned = false;
   bool autotune = true;
   int face_precond = 1;          // 0 diag(M)^-1, 1 truncated Neumann series of M^-1
@@ -371,11 +372,11 @@ spde_status get_graph(Ctx* c, const View& V, int batch, hipStream_t st, hipGraph
   return SPDE_OK;
 }
 
-// One poll interval of iterations for the slots of V (a captured graph if
-// graphs are on, else plain launches).
-spde_status enqueue_block(Ctx* c, const View& V, int batch, hipStream_t st, bool graphs, int iter0) {
+// `count` iterations for the slots of V: a captured graph if graphs are on
+// and count is the poll interval, else plain launches.
+spde_status enqueue_block(Ctx* c, const View& V, int batch, hipStream_t st, bool graphs, int iter0, int count) {
   hipGraphExec_t ex = nullptr;
-  if (graphs && get_graph(c, V, batch, st, &ex) != SPDE_OK) {
+  if (graphs && count == c->poll && get_graph(c, V, batch, st, &ex) != SPDE_OK) {
     // capture not available on this stream: fall back to plain launches
     hipGetLastError();
     c->use_graphs = false;
@@ -385,7 +386,7 @@ spde_status enqueue_block(Ctx* c, const View& V, int batch, hipStream_t st, bool
     HIPCHK(hipGraphLaunch(ex, st));
     return SPDE_OK;
   }
-  for (int k = 0; k < c->poll; ++k) {
+  for (int k = 0; k < count; ++k) {
     spde_status s = enqueue_iteration(c, V, batch, st, iter0 + k + 1);
     if (s != SPDE_OK) return s;
   }
@@ -752,15 +753,20 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* 
   const int cap = c->max_iter + 2;
   bool all_done = false;
   while (!all_done && launched < cap + c->poll) {
-    s = enqueue_block(c, V0, b1, st, graphs, launched);
+    // Blocks of poll-interval iterations; the block that would pass the
+    // iteration count at which the previous call finished stops there, so that
+    // a batch like the last one is not carried through idle iterations.
+    int count = c->poll;
+    if (c->expect_iters > launched) count = std::min(count, c->expect_iters - launched);
+    s = enqueue_block(c, V0, b1, st, graphs, launched, count);
     if (s != SPDE_OK) return s;
     if (split) {
-      s = enqueue_block(c, V1, batch - b1, c->aux_stream, graphs, launched);
+      s = enqueue_block(c, V1, batch - b1, c->aux_stream, graphs, launched, count);
       if (s != SPDE_OK) return s;
       HIPCHK(hipEventRecord(c->ev_join, c->aux_stream));
       HIPCHK(hipStreamWaitEvent(st, c->ev_join, 0));
     }
-    launched += c->poll;
+    launched += count;
     HIPCHK(hipMemcpyAsync(c->host_sc, c->F.sc, batch * sizeof(Scalars), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     all_done = true;
@@ -770,12 +776,16 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* 
     }
   }
   bool notconv = false, failed = false;
+  int most = 0;
   for (int b = 0; b < batch; ++b) {
     const Scalars& sc = c->host_sc[b];
     if (sc.state == ST_FAILED) failed = true;
     if (sc.state == ST_ACTIVE || (sc.flags & FL_NOTCONV)) notconv = true;
     if (iters_host) iters_host[b] = sc.state == ST_ACTIVE ? launched : sc.iters;
+    if (sc.state == ST_FINISH || sc.state == ST_DONE) most = std::max(most, sc.iters);
   }
+  // a converged sample needs its iterations plus the finishing pass
+  c->expect_iters = (!notconv && !failed && most > 0) ? most + 1 : 0;
   HIPCHK(launch_fix_solution(c->F, bx, batch, 0, st));
   if (u_box_dev) HIPCHK(hipMemcpyAsync(u_box_dev, c->F.x, (size_t)batch * bx.nc * 8, hipMemcpyDeviceToDevice, st));
   if (sigma_dev || relres_host) {
