@@ -32,7 +32,7 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("spde_kernels.hip", "spde_launch.inc", "spde_internal.h"):
+    for f in ("spde_kernels.hip", "spde_vcycle.inc", "spde_launch.inc", "spde_internal.h"):
         with open(os.path.join(ROOT, "paper_1712_06758_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
