@@ -200,6 +200,17 @@ def main():
             results[prec]["batch1_samples_per_s"] = float("nan")
             del box
             continue
+        # the same batch with the noise drawn inside the initialisation kernel
+        # (counter-based generator) instead of read from memory
+        sd_steps = max(3, args.steps // 2)
+        box.sample_seeded(2024, 0, w.batch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(sd_steps):
+            box.sample_seeded(2024, k * w.batch, w.batch)
+        torch.cuda.synchronize()
+        results[prec]["seeded_samples_per_s"] = w.batch * sd_steps / (time.perf_counter() - t0)
+        log(f"{prec}: generated noise: {results[prec]['seeded_samples_per_s']:.1f} samples/s")
         info = box.info()
         results[prec]["info"] = info
         del box
@@ -251,6 +262,8 @@ def main():
         "fp64_samples_per_s": round(fp["samples_per_s"], 2),
         "fp64_batch1_samples_per_s": round(fp["batch1_samples_per_s"], 2),
         "mixed_batch1_samples_per_s": round(mx["batch1_samples_per_s"], 2),
+        "device_noise_samples_per_s": {"mixed": round(mx["seeded_samples_per_s"], 2),
+                                       "fp64": round(fp["seeded_samples_per_s"], 2)},
         "mixed_over_fp64": round(mx["samples_per_s"] / fp["samples_per_s"], 3),
         "batched_mixed_over_plain_fp64_batch1": round(mx["samples_per_s"] / fp["batch1_samples_per_s"], 3),
         "iterations": {"mixed": mx["iters_mean"], "fp64": fp["iters_mean"]},

@@ -159,6 +159,44 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev,
 spde_status spde_restrict_noise(int n_fine, int batch, const double* xi_f_dev,
                                 double* xi_c_dev, void* stream);
 
+/* ---- counter-based noise --------------------------------------------------
+ * The noise xi of eq. linsys can be drawn on the device instead of being read
+ * from memory (the paper draws it on the host with a parallel pseudo-random
+ * library, Sec. "Implementation details").  Every value is a pure function of
+ * (seed, event, grid, cell), so a field is reproducible from its key alone.
+ *   Generator: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC 2011).
+ *   Field of event e on the n^3 box: key (seed, e), counter (c >> 2, n, 0, 0)
+ *     for cell c; the call's four 64-bit words x0..x3 give, by Box-Muller,
+ *     xi[4b + 0, 1] from (x0, x1) and xi[4b + 2, 3] from (x2, x3), with
+ *     u = ((x_a >> 11) + 1) 2^-53, t = (x_b >> 11) 2^-53,
+ *     (xi_a, xi_b) = sqrt(-2 ln u) (cos 2 pi t, sin 2 pi t).
+ *   Coupled field (coupled = 1): the noise of the coarse sample of event e
+ *     (eq. ml-linsys), i.e. spde_restrict_noise applied to the event's
+ *     (2n)^3 field; drawing it directly gives bitwise the same values.
+ * Raw words are integers (bitwise reproducible); normals use the device's
+ * float64 log, sqrt and sincos (a few ulp from any other libm). */
+
+/* Like spde_sample, with the noise of events event0 .. event0 + batch - 1
+ * drawn inside the initialisation kernel (nothing is read for xi).
+ * n must be divisible by 4 (coupled = 0) or even (coupled = 1); relres_host
+ * draws the noise again into workspace.  Errors as spde_sample. */
+spde_status spde_sample_seeded(spde_handle h, int batch, uint64_t seed, uint64_t event0,
+                               int coupled, double* u_tet_dev, double* u_box_dev,
+                               double* sigma_dev, void* stream, int* iters_host,
+                               double* relres_host);
+
+/* Write the noise of events event0 .. event0 + batch - 1 on the n^3 box:
+ * xi_dev [batch][n^3].  n in [2, 1024], divisible by 4 (coupled = 0) or even
+ * (coupled = 1); batch in [1, 65535].  Asynchronous on `stream`. */
+spde_status spde_noise(int n, int coupled, uint64_t seed, uint64_t event0, int batch,
+                       double* xi_dev, void* stream);
+
+/* Raw generator output for the counters (ctr0 + b, ctr1, 0, 0) under the key
+ * (seed, event): out_dev [nblocks][4] uint64, b < nblocks (1 <= nblocks <= 2^36).
+ * For checking the generator against its definition.  Asynchronous. */
+spde_status spde_philox4x64(uint64_t seed, uint64_t event, uint64_t ctr0, uint64_t ctr1,
+                            int64_t nblocks, uint64_t* out_dev, void* stream);
+
 /* ---- continuous batching (serving) ---------------------------------------
  * The slots [0, max_batch) of a handle are independent MINRES instances on the
  * same box.  A caller may start a new sample in an idle slot at any time while
@@ -173,6 +211,11 @@ spde_status spde_slots_reset(spde_handle h, int nslots, void* stream);
 /* Start a sample in `slot` from the noise xi_dev [n^3] (the slot must be idle
  * or finished).  Asynchronous on `stream`. */
 spde_status spde_slot_start(spde_handle h, int slot, const double* xi_dev, void* stream);
+
+/* Like spde_slot_start, with the noise of `event` (coupled: the coarse noise
+ * of the event) drawn inside the initialisation kernel; see spde_noise. */
+spde_status spde_slot_start_seeded(spde_handle h, int slot, uint64_t seed, uint64_t event,
+                                   int coupled, void* stream);
 
 /* Enqueue `iters` MINRES iterations over slots [0, nslots); idle and finished
  * slots are skipped on the device.  Asynchronous on `stream`. */

@@ -18,7 +18,7 @@ import numpy as np
 from . import _abi
 from ._abi import SpdeError, SPDE_FP64, SPDE_MIXED, SPDE_OK, SPDE_ENOTCONV, SPDE_EFAILED  # noqa: F401
 
-__all__ = ["Box", "restrict_noise", "g_unit_variance", "SpdeError", "build_transfer_host",
+__all__ = ["Box", "restrict_noise", "noise", "philox4x64", "g_unit_variance", "SpdeError", "build_transfer_host",
            "kernel_names", "SPDE_FP64", "SPDE_MIXED"]
 
 
@@ -115,6 +115,34 @@ def restrict_noise(xi_f, n_fine: int):
     return out
 
 
+_U64 = (1 << 64) - 1
+
+
+def noise(n: int, seed: int, event0: int = 0, batch: int = 1, coupled: bool = False, device=None):
+    """Counter-based N(0, 1) noise of the events event0 .. event0 + batch - 1 on
+    the n^3 box, drawn on the device: [batch, n^3] float64.  coupled: the noise
+    of the coarse sample of each event (the restriction of its (2n)^3 field)."""
+    torch = _torch()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty((int(batch), int(n) ** 3), dtype=torch.float64, device=dev)
+    with torch.cuda.device(dev):
+        _abi.check(_abi.lib().spde_noise(int(n), int(bool(coupled)), int(seed) & _U64, int(event0) & _U64,
+                                         int(batch), _ptr(out), _stream_ptr(dev)))
+    return out
+
+
+def philox4x64(seed: int, event: int, ctr0: int, ctr1: int, nblocks: int, device=None):
+    """Raw generator words for the counters (ctr0 + b, ctr1, 0, 0) under the key
+    (seed, event): [nblocks, 4] int64 tensor holding the uint64 bit patterns."""
+    torch = _torch()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty((int(nblocks), 4), dtype=torch.int64, device=dev)
+    with torch.cuda.device(dev):
+        _abi.check(_abi.lib().spde_philox4x64(int(seed) & _U64, int(event) & _U64, int(ctr0) & _U64,
+                                              int(ctr1) & _U64, int(nblocks), _ptr(out), _stream_ptr(dev)))
+    return out
+
+
 class Box:
     """A resident sampler for the n^3 unit box.
 
@@ -177,10 +205,25 @@ class Box:
         Returns a dict with "u_tet" [B, n_tet] (if a mesh is set and u_tet),
         "u_box" [B, n^3], "sigma" [B, 3 n^2 (n+1)], "iters" (numpy int32 [B]),
         "relres" (numpy float64 [B]) and "status"."""
-        torch = _torch()
         B = xi.shape[0]
+        _check_dev_f64(xi, (B, self.n ** 3), "xi")
+        return self._run(B, lambda *a: _abi.lib().spde_sample(self._hh.h, B, _ptr(xi), *a),
+                         u_tet, u_box, sigma, relres, allow_notconv)
+
+    def sample_seeded(self, seed: int, event0: int = 0, batch: int = 1, coupled: bool = False, u_tet=True,
+                      u_box=False, sigma=False, relres=False, allow_notconv=False):
+        """Fields for the events event0 .. event0 + batch - 1 of `seed`, with the
+        noise drawn on the device by the counter-based generator (see noise());
+        coupled: the coarse sample of each event (restriction of its (2n)^3
+        noise).  Same outputs as sample()."""
+        B = int(batch)
+        return self._run(B, lambda *a: _abi.lib().spde_sample_seeded(
+            self._hh.h, B, int(seed) & _U64, int(event0) & _U64, int(bool(coupled)), *a),
+            u_tet, u_box, sigma, relres, allow_notconv)
+
+    def _run(self, B, call, u_tet, u_box, sigma, relres, allow_notconv):
+        torch = _torch()
         nc = self.n ** 3
-        _check_dev_f64(xi, (B, nc), "xi")
         out = {}
         kw = dict(dtype=torch.float64, device=self.device)
         t_tet = torch.empty((B, self.n_tet), **kw) if (u_tet and self.n_tet) else None
@@ -189,10 +232,9 @@ class Box:
         iters = np.zeros(B, dtype=np.int32)
         rel = np.zeros(B, dtype=np.float64) if relres else None
         with torch.cuda.device(self.device):
-            st = _abi.lib().spde_sample(
-                self._hh.h, B, _ptr(xi), _ptr(t_tet), _ptr(t_box), _ptr(t_sig), _stream_ptr(self.device),
-                iters.ctypes.data_as(C.c_void_p),
-                rel.ctypes.data_as(C.c_void_p) if rel is not None else None)
+            st = call(_ptr(t_tet), _ptr(t_box), _ptr(t_sig), _stream_ptr(self.device),
+                      iters.ctypes.data_as(C.c_void_p),
+                      rel.ctypes.data_as(C.c_void_p) if rel is not None else None)
         allow = (SPDE_OK, SPDE_ENOTCONV) if allow_notconv else (SPDE_OK,)
         _abi.check(st, allow)
         out["status"] = st

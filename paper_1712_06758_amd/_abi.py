@@ -33,6 +33,10 @@ SIGNATURES = {
     "spde_set_transfer": (C.c_int, [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp]),
     "spde_sample": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "spde_restrict_noise": (C.c_int, [C.c_int, C.c_int, _vp, _vp, _vp]),
+    "spde_sample_seeded": (C.c_int, [_vp, C.c_int, C.c_uint64, C.c_uint64, C.c_int, _vp, _vp, _vp, _vp, _vp,
+                                     _vp]),
+    "spde_noise": (C.c_int, [C.c_int, C.c_int, C.c_uint64, C.c_uint64, C.c_int, _vp, _vp]),
+    "spde_philox4x64": (C.c_int, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64, _vp, _vp]),
     "spde_apply_operator": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp, _vp]),
     "spde_apply_vcycle": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "spde_apply_transfer": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
@@ -50,6 +54,7 @@ SIGNATURES = {
     "spde_info": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "spde_slots_reset": (C.c_int, [_vp, C.c_int, _vp]),
     "spde_slot_start": (C.c_int, [_vp, C.c_int, _vp, _vp]),
+    "spde_slot_start_seeded": (C.c_int, [_vp, C.c_int, C.c_uint64, C.c_uint64, C.c_int, _vp]),
     "spde_slots_step": (C.c_int, [_vp, C.c_int, C.c_int, _vp]),
     "spde_slots_poll": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "spde_slot_finish": (C.c_int, [_vp, C.c_int, _vp, _vp]),

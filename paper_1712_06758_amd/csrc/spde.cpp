@@ -718,14 +718,29 @@ spde_status spde_set_transfer(spde_handle h, int64_t n_tet, int64_t nnz, const i
   return SPDE_OK;
 }
 
-spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* u_tet_dev, double* u_box_dev,
+namespace {
+
+// Where a sample's noise comes from: device memory, or the counter-based
+// generator (events event0, event0 + 1, ... of `seed`; coupled = the
+// restriction of each event's (2n)^3 field).
+struct NoiseSrc {
+  const double* xi = nullptr;
+  uint64_t seed = 0, event0 = 0;
+  int coupled = 0;
+};
+
+spde_status check_noise_grid(const Ctx* c, int coupled) {
+  if (!coupled && (c->n % 4)) return fail(SPDE_EINVAL, "generated noise needs n divisible by 4, got %d", c->n);
+  if (coupled && (c->n % 2)) return fail(SPDE_EINVAL, "coupled noise needs an even n, got %d", c->n);
+  return SPDE_OK;
+}
+
+spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_dev, double* u_box_dev,
                         double* sigma_dev, void* stream, int* iters_host, double* relres_host) {
-  Ctx* c = reinterpret_cast<Ctx*>(h);
   spde_status s = check_ready(c);
   if (s != SPDE_OK) return s;
   if (batch < 1) return fail(SPDE_EINVAL, "batch must be >= 1");
   if (batch > c->max_batch) return fail(SPDE_ENOMEM, "batch %d exceeds max_batch %d", batch, c->max_batch);
-  if (!xi_dev) return fail(SPDE_EINVAL, "xi is null");
   if (u_tet_dev && !c->rp) return fail(SPDE_EINVAL, "u_tet requested but no transfer set");
   HIPCHK(hipSetDevice(c->device));
   hipStream_t st = pick_stream(c, stream);
@@ -735,7 +750,10 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* 
   if (s != SPDE_OK) return s;
   {
     Timed t(c, KID_INIT, 0, st);
-    HIPCHK(launch_init(c->F, bx, xi_dev, scale, batch, c->rtol, c->max_iter, 0, st));
+    if (src.xi) HIPCHK(launch_init(c->F, bx, src.xi, scale, batch, c->rtol, c->max_iter, 0, st));
+    else
+      HIPCHK(launch_init_gen(c->F, bx, src.seed, src.event0, src.coupled, scale, batch, c->rtol, c->max_iter, 0,
+                             st));
   }
   const bool graphs = c->use_graphs && !c->timing && st != nullptr;
   // A batch of 8 or more runs as two halves on two streams, so that the
@@ -795,9 +813,14 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* 
       HIPCHK(launch_flux(c->F.x, sig_int, sigma_dev, bx, batch, st));
     }
     if (relres_host) {
+      const double* xi = src.xi;
+      if (!xi) {   // draw the noise again into a Lanczos buffer the finished solve no longer needs
+        HIPCHK(launch_noise(bx.n, src.coupled, src.seed, src.event0, batch, c->F.vu[0], st));
+        xi = c->F.vu[0];
+      }
       {
         Timed t(c, KID_RESID, 0, st);
-        HIPCHK(launch_resid(sig_int, c->F.x, xi_dev, scale, bx, batch, c->F.part_pb, c->resid_out, st));
+        HIPCHK(launch_resid(sig_int, c->F.x, xi, scale, bx, batch, c->F.part_pb, c->resid_out, st));
       }
       HIPCHK(hipMemcpyAsync(c->host_res, c->resid_out, batch * sizeof(double), hipMemcpyDeviceToHost, st));
     }
@@ -813,6 +836,53 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* 
   close_timing(c, batch);
   if (failed) return fail(SPDE_EFAILED, "breakdown or non-finite value in some sample");
   if (notconv) return fail(SPDE_ENOTCONV, "max_iter reached for some sample");
+  return SPDE_OK;
+}
+
+}  // namespace
+
+spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* u_tet_dev, double* u_box_dev,
+                        double* sigma_dev, void* stream, int* iters_host, double* relres_host) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (!xi_dev) return fail(SPDE_EINVAL, "xi is null");
+  NoiseSrc src;
+  src.xi = xi_dev;
+  return sample_impl(c, batch, src, u_tet_dev, u_box_dev, sigma_dev, stream, iters_host, relres_host);
+}
+
+spde_status spde_sample_seeded(spde_handle h, int batch, uint64_t seed, uint64_t event0, int coupled,
+                               double* u_tet_dev, double* u_box_dev, double* sigma_dev, void* stream,
+                               int* iters_host, double* relres_host) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (coupled != 0 && coupled != 1) return fail(SPDE_EINVAL, "coupled must be 0 or 1");
+  spde_status s = check_noise_grid(c, coupled);
+  if (s != SPDE_OK) return s;
+  NoiseSrc src;
+  src.seed = seed;
+  src.event0 = event0;
+  src.coupled = coupled;
+  return sample_impl(c, batch, src, u_tet_dev, u_box_dev, sigma_dev, stream, iters_host, relres_host);
+}
+
+spde_status spde_noise(int n, int coupled, uint64_t seed, uint64_t event0, int batch, double* xi_dev,
+                       void* stream) {
+  if (coupled != 0 && coupled != 1) return fail(SPDE_EINVAL, "coupled must be 0 or 1");
+  if (n < 2 || n > 1024) return fail(SPDE_EINVAL, "n must lie in [2, 1024], got %d", n);
+  if (!coupled && (n % 4)) return fail(SPDE_EINVAL, "generated noise needs n divisible by 4, got %d", n);
+  if (coupled && (n % 2)) return fail(SPDE_EINVAL, "coupled noise needs an even n, got %d", n);
+  if (batch < 1 || batch > 65535) return fail(SPDE_EINVAL, "batch must lie in [1, 65535]");
+  if (!xi_dev) return fail(SPDE_EINVAL, "xi is null");
+  HIPCHK(launch_noise(n, coupled, seed, event0, batch, xi_dev, (hipStream_t)stream));
+  return SPDE_OK;
+}
+
+spde_status spde_philox4x64(uint64_t seed, uint64_t event, uint64_t ctr0, uint64_t ctr1, int64_t nblocks,
+                            uint64_t* out_dev, void* stream) {
+  if (nblocks < 1 || nblocks > ((int64_t)1 << 36)) return fail(SPDE_EINVAL, "nblocks out of range");
+  if (!out_dev) return fail(SPDE_EINVAL, "out is null");
+  HIPCHK(launch_philox_raw(seed, event, ctr0, ctr1, nblocks, out_dev, (hipStream_t)stream));
   return SPDE_OK;
 }
 
@@ -841,6 +911,22 @@ spde_status spde_slot_start(spde_handle h, int slot, const double* xi_dev, void*
   hipStream_t st = pick_stream(c, stream);
   const double scale = -c->g * std::pow(c->box.h, 1.5);
   HIPCHK(launch_init(c->F, c->box, xi_dev, scale, 1, c->rtol, c->max_iter, slot, st));
+  return SPDE_OK;
+}
+
+spde_status spde_slot_start_seeded(spde_handle h, int slot, uint64_t seed, uint64_t event, int coupled,
+                                   void* stream) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  spde_status s = check_ready(c);
+  if (s != SPDE_OK) return s;
+  if (slot < 0 || slot >= c->max_batch) return fail(SPDE_EINVAL, "slot out of range");
+  if (coupled != 0 && coupled != 1) return fail(SPDE_EINVAL, "coupled must be 0 or 1");
+  s = check_noise_grid(c, coupled);
+  if (s != SPDE_OK) return s;
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = pick_stream(c, stream);
+  const double scale = -c->g * std::pow(c->box.h, 1.5);
+  HIPCHK(launch_init_gen(c->F, c->box, seed, event, coupled, scale, 1, c->rtol, c->max_iter, slot, st));
   return SPDE_OK;
 }
 

@@ -130,6 +130,12 @@ int operator_blocks(const Box& bx);
 
 hipError_t launch_init(const Fields& F, const Box& bx, const double* xi, double scale, int batch, double tol,
                        int max_iter, int slot0, hipStream_t st);
+hipError_t launch_init_gen(const Fields& F, const Box& bx, uint64_t seed, uint64_t event0, int coupled,
+                           double scale, int batch, double tol, int max_iter, int slot0, hipStream_t st);
+hipError_t launch_noise(int m, int coupled, uint64_t seed, uint64_t event0, int batch, double* out,
+                        hipStream_t st);
+hipError_t launch_philox_raw(uint64_t seed, uint64_t event, uint64_t ctr0, uint64_t ctr1, int64_t nblocks,
+                             uint64_t* out, hipStream_t st);
 hipError_t launch_set_state(Scalars* sc, int slot0, int count, int state, hipStream_t st);
 hipError_t launch_mg_down(bool fp64, int shape, bool fine, const void* b0, const void* b1, void* rH,
                           const Level& L, int batch, const Scalars* sc, hipStream_t st);

@@ -173,6 +173,14 @@ __device__ __forceinline__ void gamma_delta_terms(const double* __restrict__ vs,
 // ---------------------------------------------------------------------------
 // initialisation: v_1 = F = [0; scale * xi], state reset
 
+__device__ __forceinline__ void init_scalars(const Fields& F, int slot, double tol, int max_iter) {
+  Scalars s{};
+  s.it = 1; s.pit = 0; s.state = ST_ACTIVE; s.flags = 0; s.wmode = -1;
+  s.c = s.c_prev = 1.0; s.s = s.s_prev = 0.0;
+  s.gamma_prev = 1.0; s.tol = tol; s.max_iter = max_iter; s.iters = 0;
+  F.sc[slot] = s;
+}
+
 __global__ __launch_bounds__(kBlock) void k_init(Fields F, Box bx, const double* __restrict__ xi,
                                                  double scale, int nb, double tol, int max_iter, int slot0) {
   const int rel = blockIdx.x / nb;
@@ -185,13 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Fields F, Box bx, const double*
     F.vs[1][face_off(slot, 1, bx.nc) + c] = 0.0;
     F.vs[1][face_off(slot, 2, bx.nc) + c] = 0.0;
   }
-  if (blk == 0 && threadIdx.x == 0) {
-    Scalars s{};
-    s.it = 1; s.pit = 0; s.state = ST_ACTIVE; s.flags = 0; s.wmode = -1;
-    s.c = s.c_prev = 1.0; s.s = s.s_prev = 0.0;
-    s.gamma_prev = 1.0; s.tol = tol; s.max_iter = max_iter; s.iters = 0;
-    F.sc[slot] = s;
-  }
+  if (blk == 0 && threadIdx.x == 0) init_scalars(F, slot, tol, max_iter);
 }
 
 // ---------------------------------------------------------------------------
@@ -1418,4 +1420,5 @@ __global__ __launch_bounds__(kBlock) void k_convert(const TS* __restrict__ s, TD
 }  // namespace spde
 
 #include "spde_vcycle.inc"
+#include "spde_rng.inc"
 #include "spde_launch.inc"

@@ -61,7 +61,23 @@ class Request:
     t_done: float = -1.0
     footprint: int = 0
     pending: int = 0
-    noise: object = None       # fine noise tensor (kept for verification when asked)
+    noise: object = None       # fine noise (tensor or NoiseKey), kept for verification when asked
+
+
+@dataclass(frozen=True)
+class NoiseKey:
+    """Noise of a request part, drawn on the device by the counter-based
+    generator: the event's own field (coupled = 0) or the restriction of the
+    event's field on the twice finer box (coupled = 1, the coarse part)."""
+    seed: int
+    event: int
+    coupled: int = 0
+
+
+def request_event(seed) -> int:
+    """Generator event of a request (level, index): unique per request."""
+    level, r = seed
+    return (int(level) << 40) | int(r)
 
 
 def percentile(values, q):
@@ -121,14 +137,21 @@ class GpuEngine:
         return bool(self.free)
 
     def start(self, part, xi):
+        """Start `part` in a free slot from a noise tensor [n^3] on the device or
+        from a NoiseKey (noise drawn inside the initialisation kernel)."""
         import ctypes as C
         slot = self.free.pop()
         part.slot = slot
         self.busy[slot] = part
+        L = _abi.lib()
         with self.torch.cuda.device(self.device):
+            if isinstance(xi, NoiseKey):
+                _abi.check(L.spde_slot_start_seeded(self.box._hh.h, slot, xi.seed, xi.event, xi.coupled,
+                                                    self._sp()))
+                return
             self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
             xi.record_stream(self.stream)
-            _abi.check(_abi.lib().spde_slot_start(self.box._hh.h, slot, C.c_void_p(xi.data_ptr()), self._sp()))
+            _abi.check(L.spde_slot_start(self.box._hh.h, slot, C.c_void_p(xi.data_ptr()), self._sp()))
 
     def step(self):
         if not self.busy:
@@ -352,18 +375,13 @@ class Server:
 # GPU server construction and the command-line load run
 
 
-def device_noise(n, seed, device):
-    """Seeded N(0,1) noise on the device (the request's seed picks the stream)."""
-    import torch
-    gen = torch.Generator(device=device)
-    gen.manual_seed(int(seed[0]) * 1000003 + int(seed[1]))
-    return torch.randn(n ** 3, dtype=torch.float64, device=device, generator=gen)
-
-
 def build_gpu_server(levels=(32, 64, 128, 256), corr_len=0.05, precision="mixed", slots=None,
-                     hbm_budget=None, device=None, keep_results=False, poll=4):
+                     hbm_budget=None, device=None, keep_results=False, poll=4, noise_seed=2024):
+    """Engines for the levels and their coupled coarse boxes.  A request's noise
+    is the generator field of (noise_seed, request_event(request seed)); its
+    coarse part draws the restriction of that field."""
     import torch
-    from . import g_unit_variance, restrict_noise
+    from . import g_unit_variance
     from workloads import serve_mesh
     device = torch.device(device or "cuda:0")
     kappa = 1.0 / corr_len
@@ -387,10 +405,10 @@ def build_gpu_server(levels=(32, 64, 128, 256), corr_len=0.05, precision="mixed"
         hbm_budget = sum(e.slot_bytes * e.slots for e in engines.values()) + (8 << 30)
 
     def noise_fn(level, seed):
-        return device_noise(level, seed, device)
+        return NoiseKey(int(noise_seed), request_event(seed))
 
-    def restrict_fn(xi, n):
-        return restrict_noise(xi.view(1, -1), n).view(-1)
+    def restrict_fn(key, n):
+        return NoiseKey(key.seed, key.event, 1)
 
     return Server(engines, levels, noise_fn, restrict_fn, hbm_budget, keep_results=keep_results)
 

@@ -58,6 +58,24 @@ def test_setup_validation(lib):
     lib.spde_destroy(h)
 
 
+def test_noise_entry_points_validate_before_launching(lib):
+    """Argument errors are caught on the host (no device call is made)."""
+    from paper_1712_06758_amd import _abi
+    L = _abi.lib()
+    buf = C.c_void_p(0x1000)          # never dereferenced: every call below fails validation first
+    assert L.spde_noise(6, 0, 1, 0, 1, buf, None) == -1            # not divisible by 4
+    assert L.spde_noise(7, 1, 1, 0, 1, buf, None) == -1            # coupled needs an even n
+    assert L.spde_noise(2048, 0, 1, 0, 1, buf, None) == -1
+    assert L.spde_noise(16, 2, 1, 0, 1, buf, None) == -1
+    assert L.spde_noise(16, 0, 1, 0, 0, buf, None) == -1
+    assert L.spde_noise(16, 0, 1, 0, 1, None, None) == -1
+    assert L.spde_philox4x64(1, 2, 0, 0, 0, buf, None) == -1
+    assert L.spde_philox4x64(1, 2, 0, 0, 4, None, None) == -1
+    assert L.spde_sample_seeded(None, 1, 1, 0, 0, None, None, None, None, None, None) == -1
+    assert L.spde_slot_start_seeded(None, 0, 1, 0, 0, None) == -1
+    assert L.spde_last_error()
+
+
 def test_configure_and_workspace(lib):
     st, h = setup(lib, 32)
     assert lib.spde_workspace_bytes(h) == 0          # not configured

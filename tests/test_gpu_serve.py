@@ -1,9 +1,10 @@
 """Serving on the GPU: continuous batching gives each request the same result
-alone and in the mix (bitwise), and the results match the oracle."""
+alone and in the mix (bitwise), and the results match the oracle (whose own
+generator recomputes the noise that the device drew for each request)."""
 import numpy as np
 import pytest
 
-from oracle import noise, spectral as S, transfer as T
+from oracle import noise, philox as PH, spectral as S, transfer as T
 from tests.gpu_common import rel_l2, say
 from workloads import serve_mesh
 
@@ -39,7 +40,8 @@ def test_alone_equals_mix_and_oracle():
     for seed in logged[:2]:
         r = mix[seed]
         n = r.level
-        xi = r.noise.cpu().numpy()
+        key = r.noise               # noise drawn on the device: recompute it with the oracle's generator
+        xi = PH.noise(n, key.seed, key.event)
         xyz, tets = serve_mesh(n)
         rows = np.random.default_rng(0).choice(tets.shape[0], 60, replace=False)
         u_f = S.solve_u(n, kappa, g, xi)
