@@ -26,8 +26,12 @@ arXiv:1712.06758):
 * ``stats``       continuum reference covariances (Matern nu = 1/2 reduces to
   exp(-kappa r), Sec. "Gaussian random fields").
 * ``sample``      the whole path: xi -> u_box -> u_tet.
+* ``philox``      counter-based white noise (Philox4x64-10 + Box-Muller) that the
+  device can draw where it is consumed.
+* ``variable``    the system with cell-wise coefficients kappa(x), g(x) and its
+  sparse direct solve; the Galerkin coarse kappa.
 
 All arithmetic is float64.
 """
-from . import discretize, spectral, minres, dense, noise, transfer, stats  # noqa: F401
+from . import discretize, spectral, minres, dense, noise, transfer, stats, philox, variable  # noqa: F401
 from .sample import sample, sample_box  # noqa: F401
