@@ -152,7 +152,7 @@ def main():
 
     import torch
     import paper_1712_06758_amd as P
-    from workloads import WORKLOADS, Workload
+    from workloads import WORKLOADS, Workload, coefficient_field
 
     w = WORKLOADS["box128"]
     if args.n != 128 or args.batch != 64:
@@ -211,6 +211,22 @@ def main():
         torch.cuda.synchronize()
         results[prec]["seeded_samples_per_s"] = w.batch * sd_steps / (time.perf_counter() - t0)
         log(f"{prec}: generated noise: {results[prec]['seeded_samples_per_s']:.1f} samples/s")
+        # space-dependent correlation length: kappa(x) spanning [kappa/2, 2 kappa] with
+        # g(x) for unit marginal variance, the preconditioner at the geometric-mean kappa
+        kf = coefficient_field(w.n, w.kappa / 2, 2 * w.kappa, 5)
+        box.set_coefficients(kf, np.sqrt(8 * np.pi * kf))
+        out = box.sample(xi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(sd_steps):
+            out = box.sample(xi)
+        torch.cuda.synchronize()
+        results[prec]["variable"] = {"samples_per_s": round(w.batch * sd_steps / (time.perf_counter() - t0), 2),
+                                     "iterations": float(out["iters"].mean()),
+                                     "kappa_range": [float(kf.min()), float(kf.max())],
+                                     "kappa_ref": round(box.kappa_ref, 4)}
+        box.set_coefficients()
+        log(f"{prec}: cell-wise kappa: {results[prec]['variable']}")
         info = box.info()
         results[prec]["info"] = info
         del box
@@ -264,6 +280,7 @@ def main():
         "mixed_batch1_samples_per_s": round(mx["batch1_samples_per_s"], 2),
         "device_noise_samples_per_s": {"mixed": round(mx["seeded_samples_per_s"], 2),
                                        "fp64": round(fp["seeded_samples_per_s"], 2)},
+        "cellwise_kappa": {"mixed": mx["variable"], "fp64": fp["variable"]},
         "mixed_over_fp64": round(mx["samples_per_s"] / fp["samples_per_s"], 3),
         "batched_mixed_over_plain_fp64_batch1": round(mx["samples_per_s"] / fp["batch1_samples_per_s"], 3),
         "iterations": {"mixed": mx["iters_mean"], "fp64": fp["iters_mean"]},

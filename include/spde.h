@@ -159,6 +159,30 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev,
 spde_status spde_restrict_noise(int n_fine, int batch, const double* xi_f_dev,
                                 double* xi_c_dev, void* stream);
 
+/* ---- spatially varying coefficients -----------------------------------------
+ * The SPDE (kappa(x)^2 - Laplacian) u = g(x) W with cell-wise kappa and g: the
+ * method's space-dependent correlation length and marginal variance (the
+ * advantage over circulant embedding named in Sec. "Introduction").  The
+ * (2,2) block of eq. linsys_blocks becomes -diag(kappa_c^2) W and the load
+ * -diag(g_c) W^{1/2} xi; every sample of the handle uses the same fields.
+ *   kappa_dev [n^3], g_dev [n^3]: caller-owned device arrays in cell order,
+ *     read by every later sampling call (keep them alive and unchanged while
+ *     the handle samples); NULL = the constant of spde_setup_box.  Values must
+ *     be finite, kappa > 0 and g >= 0 (not checked: a non-finite value makes
+ *     the samples fail with SPDE_EFAILED).
+ *   kappa_ref: the constant kappa of the multigrid preconditioner S~ (the
+ *     operator always uses the cell values).  Required (> 0) with a kappa
+ *     field; sqrt(kappa_min kappa_max) keeps every kappa_c^2 / kappa_ref^2
+ *     within [kappa_min / kappa_max, kappa_max / kappa_min].  0 without a
+ *     kappa field keeps the setup kappa.
+ * Coupled coarse samples (eq. ml-linsys): the Galerkin coarse reaction block
+ * has kappa_c^2 = mean of the 8 children's kappa^2; the coarse load equals the
+ * restricted one when g is constant on each coarse cell.
+ * Call between sampling calls (not while slots iterate).  Host-only: returns
+ * SPDE_EINVAL for a bad kappa_ref. */
+spde_status spde_set_coefficients(spde_handle h, const double* kappa_dev, const double* g_dev,
+                                  double kappa_ref);
+
 /* ---- counter-based noise --------------------------------------------------
  * The noise xi of eq. linsys can be drawn on the device instead of being read
  * from memory (the paper draws it on the host with a parallel pseudo-random

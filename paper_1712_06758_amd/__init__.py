@@ -198,6 +198,38 @@ class Box:
         _abi.check(L.spde_set_transfer_order(self._hh.h, _ptr(od)))
         return self.n_tet, self.nnz
 
+    # -- coefficients ------------------------------------------------------
+    def set_coefficients(self, kappa=None, g=None, kappa_ref: float | None = None):
+        """Cell-wise kappa(x) and g(x) ([n^3] float64, cell order; host arrays are
+        copied to the device, device tensors are used in place and must stay
+        alive).  kappa_ref: constant kappa of the multigrid preconditioner
+        (default for host arrays: sqrt(min kappa * max kappa); required for a
+        device kappa tensor).  set_coefficients() restores the constants."""
+        torch = _torch()
+        nc = self.n ** 3
+
+        def dev(a, name):
+            if a is None:
+                return None
+            if isinstance(a, torch.Tensor) and a.is_cuda:
+                _check_dev_f64(a.view(1, -1), (1, nc), name)
+                return a
+            arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
+            if arr.size != nc:
+                raise ValueError(f"{name} must have n^3 = {nc} entries")
+            return torch.as_tensor(arr).to(self.device)
+
+        if kappa is not None and kappa_ref is None:
+            if isinstance(kappa, torch.Tensor) and kappa.is_cuda:
+                raise ValueError("kappa_ref is required with a device kappa tensor")
+            k = np.asarray(kappa, dtype=np.float64)
+            kappa_ref = math.sqrt(float(k.min()) * float(k.max()))
+        tk, tg = dev(kappa, "kappa"), dev(g, "g")
+        _abi.check(_abi.lib().spde_set_coefficients(self._hh.h, _ptr(tk), _ptr(tg),
+                                                    float(kappa_ref or 0.0)))
+        self._coef = (tk, tg)      # the library reads them at every call
+        self.kappa_ref = kappa_ref
+
     # -- sampling ---------------------------------------------------------
     def sample(self, xi, u_tet=True, u_box=False, sigma=False, relres=False, allow_notconv=False):
         """Fields for the noise batch xi [B, n^3] (float64, on the device).

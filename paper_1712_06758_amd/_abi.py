@@ -36,6 +36,7 @@ SIGNATURES = {
     "spde_sample_seeded": (C.c_int, [_vp, C.c_int, C.c_uint64, C.c_uint64, C.c_int, _vp, _vp, _vp, _vp, _vp,
                                      _vp]),
     "spde_noise": (C.c_int, [C.c_int, C.c_int, C.c_uint64, C.c_uint64, C.c_int, _vp, _vp]),
+    "spde_set_coefficients": (C.c_int, [_vp, _vp, _vp, C.c_double]),
     "spde_philox4x64": (C.c_int, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64, _vp, _vp]),
     "spde_apply_operator": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp, _vp]),
     "spde_apply_vcycle": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),

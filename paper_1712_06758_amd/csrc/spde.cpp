@@ -71,6 +71,8 @@ struct Ctx {
   // problem
   int n = 0;
   double kappa = 0, g = 0;
+  double kappa_pre = 0;         // kappa of the multigrid preconditioner (the constant kappa, or
+                                // the reference kappa of cell-wise coefficients)
   Box box{};
   // configuration
   int prec = SPDE_FP64;
@@ -160,7 +162,7 @@ size_t coarse_bytes(const Ctx* c, int top) {
 
 void plan_hierarchy(Ctx* c) {
   c->nlev = 0;
-  for (int m = c->n; m >= 1; m >>= 1) set_level(c->lv[c->nlev++], m, c->kappa);
+  for (int m = c->n; m >= 1; m >>= 1) set_level(c->lv[c->nlev++], m, c->kappa_pre);
   // persistent kernel: the largest levels (below the finest) that fit in LDS, at most 16^3
   int top = c->nlev - 1;
   for (int l = 1; l < c->nlev; ++l) {
@@ -256,7 +258,7 @@ double slot_bytes(const Ctx* c, int kid, int level, int iter, int wmode_active) 
       // and on the finishing pass J + 1, which reads W_J and W_{J-1} and writes nothing else.
       double b = 0;
       const bool fin = (wmode_active & 4) != 0;
-      if (wmode_active & 1) b += nc * ((iter > 1 ? 64.0 : 32.0) + sz + 32.0);
+      if (wmode_active & 1) b += nc * ((iter > 1 ? 64.0 : 32.0) + sz + 32.0 + (c->box.kap ? 8.0 : 0.0));
       if ((wmode_active & 2) && !fin) b += nc * (8.0 + (iter >= 2 ? 8.0 : 0.0) + (iter >= 3 ? 8.0 : 0.0));
       if (fin) b += nc * (8.0 + (iter >= 4 ? 8.0 : 0.0));
       if ((wmode_active & 2) && iter >= 2) {
@@ -265,7 +267,7 @@ double slot_bytes(const Ctx* c, int kid, int level, int iter, int wmode_active) 
       }
       return b;
     }
-    case KID_MG_UP_FINE: return nc * (8.0 + sz / 8.0 + 24.0 + sz);
+    case KID_MG_UP_FINE: return nc * (8.0 + sz / 8.0 + 24.0 + sz + (c->box.kap ? 8.0 : 0.0));
     case KID_MG_DOWN_FINE: return nc * (8.0 + sz / 8.0);
     case KID_MG_DOWN: { const double m = (double)c->lv[level].nc; return m * (sz + sz / 8.0); }
     case KID_MG_UP: { const double m = (double)c->lv[level].nc; return m * (sz + sz / 8.0 + sz); }
@@ -598,6 +600,7 @@ spde_status spde_setup_box(int n, double kappa, double g, spde_handle* out) {
   Ctx* c = new Ctx();
   c->n = n;
   c->kappa = kappa;
+  c->kappa_pre = kappa;
   c->g = g;
   Box& b = c->box;
   b.n = n;
@@ -610,6 +613,9 @@ spde_status spde_setup_box(int n, double kappa, double g, spde_handle* out) {
   b.g = g;
   b.q = 1.5 / b.h3;
   b.k2h3 = kappa * kappa * b.h3;
+  b.h15 = std::pow(b.h, 1.5);
+  b.kap = nullptr;
+  b.gfld = nullptr;
   b.h2q = b.h2 * b.q;
   *out = reinterpret_cast<spde_handle>(c);
   return SPDE_OK;
@@ -633,6 +639,23 @@ spde_status spde_configure(spde_handle h, spde_precision prec, double rtol, int 
   c->ws_bytes = 0;
   c->tuned = false;
   plan_hierarchy(c);
+  return SPDE_OK;
+}
+
+spde_status spde_set_coefficients(spde_handle h, const double* kappa_dev, const double* g_dev, double kappa_ref) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (kappa_dev && !(kappa_ref > 0.0 && std::isfinite(kappa_ref)))
+    return fail(SPDE_EINVAL, "kappa_ref must be positive and finite with a kappa field");
+  if (!kappa_dev && kappa_ref != 0.0 && !(kappa_ref > 0.0 && std::isfinite(kappa_ref)))
+    return fail(SPDE_EINVAL, "kappa_ref must be 0 or positive and finite");
+  drop_graphs(c);   // kernel arguments change
+  c->box.kap = kappa_dev;
+  c->box.gfld = g_dev;
+  c->kappa_pre = kappa_dev ? kappa_ref : (kappa_ref > 0.0 ? kappa_ref : c->kappa);
+  // new level coefficients of the preconditioner; shapes, tiles and layout stay
+  for (int l = 0; l < c->nlev; ++l) set_level(c->lv[l], c->lv[l].m, c->kappa_pre);
+  for (int l = c->top; l < c->nlev; ++l) c->cp.lv[l - c->top] = c->lv[l];
   return SPDE_OK;
 }
 

@@ -73,7 +73,25 @@ struct Box {
   double k2h3;       // kappa^2 h^3
   double h2q;        // h^2 q
   int poly;          // face block of the preconditioner: 0 diag(M)^-1, 1 q (I - S + S^2)
+  // Cell-wise coefficients (caller-owned device arrays [n^3], null: the
+  // constants above): the operator's reaction term is kap_c^2 h^3 and the load
+  // factor -g_c h^{3/2}; the multigrid preconditioner keeps a constant kappa.
+  const double* kap;
+  const double* gfld;
+  double h15;        // h^{3/2}
 };
+
+// kappa^2 h^3 of cell c (same rounding as the host's kappa * kappa * h^3).
+// VAR: cell-wise kappa (a compile-time choice in the hot kernels, so that the
+// constant path carries no branch); the run-time form serves the others.
+template <bool VAR>
+__host__ __device__ inline double cell_k2h3(const Box& b, int64_t c) {
+  if constexpr (VAR) return (b.kap[c] * b.kap[c]) * b.h3;
+  else return b.k2h3;
+}
+__host__ __device__ inline double cell_k2h3(const Box& b, int64_t c) {
+  return b.kap ? cell_k2h3<true>(b, c) : b.k2h3;
+}
 
 // One multigrid level: operator S~ = k2 I + a L (L the Neumann graph
 // Laplacian), Chebyshev smoother coefficients of the degree-2 polynomial.

@@ -131,7 +131,7 @@ __device__ __forceinline__ void line_terms(const double* w, int i, int n, int po
 // The same contributions from line values already gathered (wx, wy, wz hold
 // v_{f+k}, k = -3..3, along x, y, z; zero outside the interior faces).
 __device__ __forceinline__ void gamma_delta_lines(const double* wx, const double* wy, const double* wz, int x, int y,
-                                                  int z, const Box& bx, double vu, double zc, double& gg,
+                                                  int z, const Box& bx, double vu, double zc, double k2, double& gg,
                                                   double& dg) {
   const int n = bx.n;
   const double* ws[3] = {wx, wy, wz};
@@ -146,11 +146,12 @@ __device__ __forceinline__ void gamma_delta_lines(const double* wx, const double
     dv += zh - zf;
   }
   gg += bx.q * sv + zc * vu;
-  dg += bx.q * szm + 2.0 * zc * bx.h2q * dv - bx.k2h3 * zc * zc;
+  dg += bx.q * szm + 2.0 * zc * bx.h2q * dv - k2 * zc * zc;
 }
 
 __device__ __forceinline__ void gamma_delta_terms(const double* __restrict__ vs, int64_t g, int x, int y, int z,
-                                                  const Box& bx, double vu, double zc, double& gg, double& dg) {
+                                                  const Box& bx, double vu, double zc, double k2, double& gg,
+                                                  double& dg) {
   const int n = bx.n;
   const int64_t nc = bx.nc;
   const int idx[3] = {x, y, z};
@@ -167,7 +168,7 @@ __device__ __forceinline__ void gamma_delta_terms(const double* __restrict__ vs,
     dv += zh - zf;        // (B P^-1 v)_cell / (h^2 q)
   }
   gg += bx.q * sv + zc * vu;
-  dg += bx.q * szm + 2.0 * zc * bx.h2q * dv - bx.k2h3 * zc * zc;
+  dg += bx.q * szm + 2.0 * zc * bx.h2q * dv - k2 * zc * zc;
 }
 
 // ---------------------------------------------------------------------------
@@ -188,7 +189,8 @@ __global__ __launch_bounds__(kBlock) void k_init(Fields F, Box bx, const double*
   const int blk = blockIdx.x - rel * nb;
   const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
   if (c < bx.nc) {
-    F.vu[1][cell_off(slot, bx.nc) + c] = scale * xi[cell_off(rel, bx.nc) + c];
+    const double sc_c = bx.gfld ? -bx.gfld[c] * bx.h15 : scale;
+    F.vu[1][cell_off(slot, bx.nc) + c] = sc_c * xi[cell_off(rel, bx.nc) + c];
     F.vs[1][face_off(slot, 0, bx.nc) + c] = 0.0;
     F.vs[1][face_off(slot, 1, bx.nc) + c] = 0.0;
     F.vs[1][face_off(slot, 2, bx.nc) + c] = 0.0;
@@ -324,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_down(const TB* __restrict__ b0, c
 //   <zhat, v_u>  and  zhat^T A zhat  with zhat = (diag(M)^-1 v_sigma, zhat_u),
 // from which the scalar step forms gamma_j and delta_j.
 
-template <typename TM, typename TB, typename TO, int TX, int TY, int TZ, bool FINE>
+template <typename TM, typename TB, typename TO, int TX, int TY, int TZ, bool FINE, bool VAR = false>
 __global__ __launch_bounds__(kBlock) void k_mg_up(const TB* __restrict__ b0, const TB* __restrict__ b1,
                                                   const TM* __restrict__ eH, TO* __restrict__ o0,
                                                   TO* __restrict__ o1, Level L, int nb,
@@ -438,7 +440,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_up(const TB* __restrict__ b0, con
     const TO zo = (TO)out;
     o[g] = zo;
     if (FINE && part)
-      gamma_delta_terms(vs + face_off(slot, 0, bxc.nc), g, gx, gy, gz, bxc, (double)b[g], (double)zo, p_zv, p_azz);
+      gamma_delta_terms(vs + face_off(slot, 0, bxc.nc), g, gx, gy, gz, bxc, (double)b[g], (double)zo,
+                        cell_k2h3<VAR>(bxc, g), p_zv, p_azz);
   }
   if (FINE && part) {
     p_zv = block_sum(p_zv, red);
@@ -576,7 +579,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_down_zs(const TB* __restrict__ b0
   }
 }
 
-template <typename TM, typename TB, typename TO, int TX, int TY, int ZC, bool FINE>
+template <typename TM, typename TB, typename TO, int TX, int TY, int ZC, bool FINE, bool VAR = false>
 __global__ __launch_bounds__(kBlock, 4) void k_mg_up_zs(const TB* __restrict__ b0, const TB* __restrict__ b1,
                                                      const TM* __restrict__ eH, TO* __restrict__ o0,
                                                      TO* __restrict__ o1, Level L, int nb,
@@ -803,7 +806,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_mg_up_zs(const TB* __restrict__ b
           wx[k] = fxp[tx + k + FXW * ty];
           wy[k] = fyp[tx + TX * (ty + k)];
         }
-        gamma_delta_lines(wx, wy, wzl, gx, gy, zo, bxc, (double)b[g], (double)zo_v, p_zv, p_azz);
+        gamma_delta_lines(wx, wy, wzl, gx, gy, zo, bxc, (double)b[g], (double)zo_v, cell_k2h3<VAR>(bxc, g), p_zv, p_azz);
       }
     }
     __syncthreads();
@@ -1072,7 +1075,8 @@ __device__ __forceinline__ void line_terms_ext(const double* w, int poly, double
 // positions, and with them the y- and z-window offsets, are wave-uniform.
 // POLY: face block of the preconditioner (0 diag(M)^-1, 1 Neumann series), a
 // template parameter so that no window load sits behind a branch on it.
-template <typename TZ, bool UNI, int POLY>
+// VAR: cell-wise kappa (the reaction term kappa_c^2 h^3 of the cell row).
+template <typename TZ, bool UNI, int POLY, bool VAR>
 __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int slot = lb / nb, blk = lb - slot * nb;
@@ -1138,6 +1142,8 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
   }
   const double vuc = F.vu[p][co + c], vuo = F.vu[pq][co + c];
   const double wj = F.w[pq][co + c], wjm1 = F.w[p][co + c];
+  // VAR: cell-wise kappa (shared by the slots), read with the other loads
+  const double kc = VAR ? bx.kap[c] : 0.0;
 
   double dv = 0.0, nf[3];
 #pragma unroll
@@ -1151,7 +1157,8 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d) F.vs[pq][face_off(slot, d, nc) + c] = nf[d];
-  const double Au = zs * (bx.h2q * dv - bx.k2h3 * zc);
+  const double k2 = VAR ? (kc * kc) * bx.h3 : bx.k2h3;
+  const double Au = zs * (bx.h2q * dv - k2 * zc);
   const double nu = Au - av * vuc;
   F.vu[pq][co + c] = has_prev ? nu - bv * vuo : nu;
   double wn = zs * zc;
@@ -1269,8 +1276,9 @@ __global__ __launch_bounds__(kBlock) void k_resid(const double* __restrict__ sig
     const double div = ((i < n - 1 ? sx[c + 1] : 0.0) - sx[c]) + ((j < n - 1 ? sy[c + n] : 0.0) - sy[c]) +
                        ((k < n - 1 ? sz[c + bx.n2] : 0.0) - sz[c]);
     const double uc = u[cell_off(slot, nc) + c];
-    const double fu = scale * xi[cell_off(slot, nc) + c];
-    const double r = fu - (bx.h2 * div - bx.k2h3 * uc);
+    const double sc_c = bx.gfld ? -bx.gfld[c] * bx.h15 : scale;
+    const double fu = sc_c * xi[cell_off(slot, nc) + c];
+    const double r = fu - (bx.h2 * div - cell_k2h3(bx, c) * uc);
     rr = r * r;
     ff = fu * fu;
   }

@@ -76,6 +76,21 @@ def test_noise_entry_points_validate_before_launching(lib):
     assert L.spde_last_error()
 
 
+def test_set_coefficients_validation(lib):
+    from paper_1712_06758_amd import _abi
+    L = _abi.lib()
+    assert L.spde_set_coefficients(None, None, None, 0.0) == -1
+    st, h = setup(lib, 16)
+    assert st == 0
+    fake = C.c_void_p(0x1000)          # stored only; nothing reads it without a sampling call
+    assert L.spde_set_coefficients(h, fake, None, 0.0) == -1        # kappa field needs kappa_ref
+    assert L.spde_set_coefficients(h, fake, None, float("nan")) == -1
+    assert L.spde_set_coefficients(h, None, None, -2.0) == -1
+    assert L.spde_set_coefficients(h, fake, fake, 7.0) == 0
+    assert L.spde_set_coefficients(h, None, None, 0.0) == 0
+    lib.spde_destroy(h)
+
+
 def test_configure_and_workspace(lib):
     st, h = setup(lib, 32)
     assert lib.spde_workspace_bytes(h) == 0          # not configured

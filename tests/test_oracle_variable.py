@@ -6,20 +6,7 @@ import pytest
 
 from oracle import discretize as D, minres as MR, spectral as S, variable as V
 from tests.test_oracle_discretize import p0_injection, rt0_prolongation
-
-
-def smooth_field(n, lo, hi, seed):
-    """A smooth positive cell field with values in [lo, hi]."""
-    rng = np.random.default_rng(seed)
-    x = (np.arange(n) + 0.5) / n
-    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
-    f = np.zeros_like(X)
-    for _ in range(4):
-        a, b, c = rng.uniform(0.5, 2.5, 3)
-        ph = rng.uniform(0, 2 * np.pi, 3)
-        f += np.cos(np.pi * a * X + ph[0]) * np.cos(np.pi * b * Y + ph[1]) * np.cos(np.pi * c * Z + ph[2])
-    f = (f - f.min()) / (f.max() - f.min())
-    return (lo * (hi / lo) ** f).reshape(-1)
+from workloads import coefficient_field as smooth_field
 
 
 @pytest.mark.parametrize("n", [4, 8])

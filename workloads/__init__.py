@@ -51,6 +51,23 @@ KUHN = np.array([
 ], dtype=np.int64)
 
 
+def coefficient_field(n: int, lo: float, hi: float, seed: int) -> np.ndarray:
+    """A smooth positive cell field on the n^3 box with values spanning [lo, hi]
+    (cell order, x fastest): lo (hi/lo)^f with f in [0, 1] a normalised sum of
+    four products of cosines with random wave numbers (0.5 to 2.5 half-waves
+    per unit length) and phases.  Input for cell-wise kappa(x) or g(x)."""
+    rng = np.random.default_rng(seed)
+    x = (np.arange(n) + 0.5) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    f = np.zeros_like(X)
+    for _ in range(4):
+        a, b, c = rng.uniform(0.5, 2.5, 3)
+        ph = rng.uniform(0, 2 * np.pi, 3)
+        f += np.cos(np.pi * a * X + ph[0]) * np.cos(np.pi * b * Y + ph[1]) * np.cos(np.pi * c * Z + ph[2])
+    f = (f - f.min()) / (f.max() - f.min())
+    return (lo * (hi / lo) ** f).reshape(-1)
+
+
 def kuhn_tets(m: int) -> np.ndarray:
     """Connectivity [6 m^3, 4] of the Kuhn split of an m^3 grid of cubes.
 
