@@ -113,6 +113,19 @@ spde_status spde_build_transfer(spde_handle h, int64_t n_vert, const double* xyz
                                 int64_t** row_ptr_host, int32_t** col_host,
                                 double** val_host, int64_t* nnz);
 
+/* Pi of the coupled coarse box ((n_fine/2)^3) onto the same tet mesh, from Pi
+ * of the n_fine^3 box (eq. recursive_l2_projection, G_{l+1} = G_l P with the
+ * box hierarchy's P0 injection P; the tet mesh is not coarsened):
+ * Pi_c[t, I] = sum over the 8 children c of coarse cell I of Pi_f[t, c],
+ * exact since a tet's overlap with I is the sum of its overlaps with the
+ * children.  Input CSR in host memory (columns in [0, n_fine^3)); outputs as
+ * spde_build_transfer (ascending columns, release with spde_free_host).
+ * n_fine even in [2, 1024].  SPDE_EINVAL on a malformed matrix.  Host-only. */
+spde_status spde_transfer_coarsen(int n_fine, int64_t n_rows, const int64_t* row_ptr_host,
+                                  const int32_t* col_host, const double* val_host,
+                                  int64_t** row_ptr_c, int32_t** col_c, double** val_c,
+                                  int64_t* nnz_c);
+
 /* Register a device copy of Pi (CSR as produced above).  The arrays are
  * borrowed, not copied: they must stay valid while the handle samples. */
 spde_status spde_set_transfer(spde_handle h, int64_t n_tet, int64_t nnz,

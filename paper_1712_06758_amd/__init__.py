@@ -19,6 +19,7 @@ from . import _abi
 from ._abi import SpdeError, SPDE_FP64, SPDE_MIXED, SPDE_OK, SPDE_ENOTCONV, SPDE_EFAILED  # noqa: F401
 
 __all__ = ["Box", "restrict_noise", "noise", "philox4x64", "g_unit_variance", "SpdeError", "build_transfer_host",
+           "coarsen_transfer_host",
            "kernel_names", "SPDE_FP64", "SPDE_MIXED"]
 
 
@@ -93,6 +94,32 @@ def build_transfer_host(n: int, xyz: np.ndarray, tets: np.ndarray):
         L.spde_free_host(C.cast(ci, C.c_void_p))
         L.spde_free_host(C.cast(cv, C.c_void_p))
     return row_ptr, cols, vals
+
+
+def coarsen_transfer_host(n_fine: int, row_ptr, cols, vals):
+    """Pi of the (n_fine/2)^3 box onto the same tet mesh from Pi of the n_fine^3
+    box (sum over each coarse cell's 8 children), by the library's host code.
+    Returns (row_ptr int64, cols int32, vals float64) numpy arrays."""
+    L = _abi.lib()
+    rp_in = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci_in = np.ascontiguousarray(cols, dtype=np.int32)
+    cv_in = np.ascontiguousarray(vals, dtype=np.float64)
+    rp = C.POINTER(C.c_int64)()
+    ci = C.POINTER(C.c_int32)()
+    cv = C.POINTER(C.c_double)()
+    nnz = C.c_int64()
+    nr = rp_in.size - 1
+    _abi.check(L.spde_transfer_coarsen(int(n_fine), nr, rp_in.ctypes.data, ci_in.ctypes.data, cv_in.ctypes.data,
+                                       C.byref(rp), C.byref(ci), C.byref(cv), C.byref(nnz)))
+    try:
+        row_ptr_c = np.ctypeslib.as_array(rp, shape=(nr + 1,)).copy()
+        cols_c = np.ctypeslib.as_array(ci, shape=(max(1, nnz.value),))[:nnz.value].copy()
+        vals_c = np.ctypeslib.as_array(cv, shape=(max(1, nnz.value),))[:nnz.value].copy()
+    finally:
+        L.spde_free_host(C.cast(rp, C.c_void_p))
+        L.spde_free_host(C.cast(ci, C.c_void_p))
+        L.spde_free_host(C.cast(cv, C.c_void_p))
+    return row_ptr_c, cols_c, vals_c
 
 
 def transfer_row_order(row_ptr, cols):

@@ -24,6 +24,9 @@ namespace spde {
 int build_transfer_csr(int n, int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tets,
                        std::vector<int64_t>& row_ptr, std::vector<int32_t>& cols, std::vector<double>& vals,
                        char* err, size_t errlen);
+int coarsen_transfer_csr(int n_fine, int64_t n_rows, const int64_t* rp, const int32_t* ci, const double* cv,
+                         std::vector<int64_t>& rp_c, std::vector<int32_t>& ci_c, std::vector<double>& cv_c,
+                         char* err, size_t errlen);
 }
 
 using namespace spde;
@@ -723,6 +726,30 @@ spde_status spde_build_transfer(spde_handle h, int64_t n_vert, const double* xyz
   memcpy(*col_host, ci.data(), ci.size() * sizeof(int32_t));
   memcpy(*val_host, cv.data(), cv.size() * sizeof(double));
   *nnz = (int64_t)ci.size();
+  return SPDE_OK;
+}
+
+spde_status spde_transfer_coarsen(int n_fine, int64_t n_rows, const int64_t* row_ptr_host, const int32_t* col_host,
+                                  const double* val_host, int64_t** row_ptr_c, int32_t** col_c, double** val_c,
+                                  int64_t* nnz_c) {
+  if (n_fine < 2 || n_fine > 1024 || (n_fine & 1)) return fail(SPDE_EINVAL, "n_fine must be even in [2, 1024]");
+  if (n_rows < 1 || !row_ptr_host || !row_ptr_c || !col_c || !val_c || !nnz_c)
+    return fail(SPDE_EINVAL, "null argument or empty matrix");
+  if (row_ptr_host[n_rows] > 0 && (!col_host || !val_host)) return fail(SPDE_EINVAL, "null column or value array");
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<double> cv;
+  char err[256] = {0};
+  if (coarsen_transfer_csr(n_fine, n_rows, row_ptr_host, col_host, val_host, rp, ci, cv, err, sizeof err) != 0)
+    return fail(SPDE_EINVAL, "%s", err);
+  *row_ptr_c = (int64_t*)malloc(rp.size() * sizeof(int64_t));
+  *col_c = (int32_t*)malloc(std::max<size_t>(1, ci.size()) * sizeof(int32_t));
+  *val_c = (double*)malloc(std::max<size_t>(1, cv.size()) * sizeof(double));
+  if (!*row_ptr_c || !*col_c || !*val_c) return fail(SPDE_ENOMEM, "host allocation failed");
+  memcpy(*row_ptr_c, rp.data(), rp.size() * sizeof(int64_t));
+  memcpy(*col_c, ci.data(), ci.size() * sizeof(int32_t));
+  memcpy(*val_c, cv.data(), cv.size() * sizeof(double));
+  *nnz_c = (int64_t)ci.size();
   return SPDE_OK;
 }
 

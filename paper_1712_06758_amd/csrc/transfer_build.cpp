@@ -209,4 +209,92 @@ int build_transfer_csr(int n, int64_t n_vert, const double* xyz, int64_t n_tet, 
   return 0;
 }
 
+// Pi of the (n_fine/2)^3 box onto the same tet mesh from Pi of the n_fine^3
+// box (eq. recursive_l2_projection with the box hierarchy's P0 injection and
+// the tet mesh kept): the overlap of a tet with a coarse cell is the sum of its
+// overlaps with the 8 children, so Pi_c[t, I] = sum over the children c of I of
+// Pi_f[t, c].  Each row's children are summed in the order of the fine row;
+// the coarse columns come out ascending.  Returns 0, or -1 on invalid input.
+int coarsen_transfer_csr(int n_fine, int64_t n_rows, const int64_t* rp, const int32_t* ci, const double* cv,
+                         std::vector<int64_t>& rp_c, std::vector<int32_t>& ci_c, std::vector<double>& cv_c,
+                         char* err, size_t errlen) {
+  const int m = n_fine / 2;
+  const int64_t ncf = (int64_t)n_fine * n_fine * n_fine;
+  if (rp[0] != 0) {
+    snprintf(err, errlen, "row_ptr[0] must be 0");
+    return -1;
+  }
+  for (int64_t r = 0; r < n_rows; ++r) {
+    if (rp[r + 1] < rp[r]) {
+      snprintf(err, errlen, "row_ptr decreases at row %lld", (long long)r);
+      return -1;
+    }
+  }
+  for (int64_t k = 0; k < rp[n_rows]; ++k) {
+    if (ci[k] < 0 || ci[k] >= ncf) {
+      snprintf(err, errlen, "column %d at entry %lld lies outside the %d^3 box", ci[k], (long long)k, n_fine);
+      return -1;
+    }
+  }
+  rp_c.assign(n_rows + 1, 0);
+  std::vector<int32_t> pc(rp[n_rows]);
+  std::vector<double> pv(rp[n_rows]);
+  // rows are independent: map, stable-sort by parent, merge (in place within the row's fine range)
+  unsigned nth = std::thread::hardware_concurrency();
+  if (nth == 0) nth = 1;
+  if (nth > 64) nth = 64;
+  std::vector<int64_t> len(n_rows, 0);
+  std::atomic<int64_t> next{0};
+  const int64_t chunk = 16384;
+  auto worker = [&]() {
+    std::vector<std::pair<int32_t, int32_t>> key;   // (parent, position in the row)
+    for (;;) {
+      const int64_t r0 = next.fetch_add(chunk);
+      if (r0 >= n_rows) break;
+      const int64_t r1 = std::min(n_rows, r0 + chunk);
+      for (int64_t r = r0; r < r1; ++r) {
+        const int64_t k0 = rp[r], k1 = rp[r + 1];
+        key.clear();
+        for (int64_t k = k0; k < k1; ++k) {
+          const int32_t c = ci[k];
+          const int i = c % n_fine, j = (c / n_fine) % n_fine, kk = c / (n_fine * n_fine);
+          key.push_back({(int32_t)((i >> 1) + m * ((j >> 1) + m * (kk >> 1))), (int32_t)(k - k0)});
+        }
+        std::stable_sort(key.begin(), key.end(),
+                         [](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
+                           return a.first < b.first;
+                         });
+        int64_t out = k0;
+        for (size_t e = 0; e < key.size(); ++e) {
+          const double v = cv[k0 + key[e].second];
+          if (e > 0 && key[e].first == key[e - 1].first) {
+            pv[out - 1] += v;
+          } else {
+            pc[out] = key[e].first;
+            pv[out] = v;
+            ++out;
+          }
+        }
+        len[r] = out - k0;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (unsigned i = 0; i < nth; ++i) th.emplace_back(worker);
+  for (auto& x : th) x.join();
+  int64_t nnz = 0;
+  for (int64_t r = 0; r < n_rows; ++r) {
+    rp_c[r] = nnz;
+    nnz += len[r];
+  }
+  rp_c[n_rows] = nnz;
+  ci_c.resize(nnz);
+  cv_c.resize(nnz);
+  for (int64_t r = 0; r < n_rows; ++r) {
+    std::memcpy(ci_c.data() + rp_c[r], pc.data() + rp[r], len[r] * sizeof(int32_t));
+    std::memcpy(cv_c.data() + rp_c[r], pv.data() + rp[r], len[r] * sizeof(double));
+  }
+  return 0;
+}
+
 }  // namespace spde

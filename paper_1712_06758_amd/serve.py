@@ -96,7 +96,7 @@ class GpuEngine:
 
     STATE_ACTIVE, STATE_DONE, STATE_NOTCONV, STATE_FAILED, STATE_IDLE = 0, 1, 2, 3, 4
 
-    def __init__(self, n, kappa, g, precision, slots, device, rtol=None, meshes=None, poll=4):
+    def __init__(self, n, kappa, g, precision, slots, device, rtol=None, meshes=None, poll=4, transfers=None):
         import torch
         from . import Box
         self.torch = torch
@@ -110,8 +110,11 @@ class GpuEngine:
         self.free = list(range(slots - 1, -1, -1))
         self.busy = {}
         self.transfers = {}           # mesh name -> (n_tet, nnz, rp, ci, cv)
+        self.host_transfers = {}
         for name, (xyz, tets) in (meshes or {}).items():
-            self.add_mesh(name, xyz, tets)
+            self.host_transfers[name] = self.add_mesh(name, xyz, tets)
+        for name, (rp, ci, cv) in (transfers or {}).items():
+            self.add_transfer(name, rp, ci, cv)
         L = _abi.lib()
         with torch.cuda.device(device), torch.cuda.stream(self.stream):
             _abi.check(L.spde_slots_reset(self.box._hh.h, slots, self._sp()))
@@ -125,11 +128,19 @@ class GpuEngine:
         return C.c_void_p(self.stream.cuda_stream)
 
     def add_mesh(self, name, xyz, tets):
-        from . import build_transfer_host, transfer_row_order
-        torch = self.torch
+        """Pi of this box onto a tet mesh, built from the geometry (host clipper);
+        returns the host CSR."""
+        from . import build_transfer_host
         rp, ci, cv = build_transfer_host(self.n, xyz, tets)
+        self.add_transfer(name, rp, ci, cv)
+        return rp, ci, cv
+
+    def add_transfer(self, name, rp, ci, cv):
+        """Register a host CSR Pi of this box onto the tet mesh `name`."""
+        from . import transfer_row_order
+        torch = self.torch
         d = self.device
-        self.transfers[name] = (tets.shape[0], ci.size, torch.as_tensor(rp).to(d),
+        self.transfers[name] = (rp.size - 1, ci.size, torch.as_tensor(rp).to(d),
                                 torch.as_tensor(ci).to(d), torch.as_tensor(cv).to(d),
                                 torch.as_tensor(transfer_row_order(rp, ci)).to(d))
 
@@ -381,7 +392,7 @@ def build_gpu_server(levels=(32, 64, 128, 256), corr_len=0.05, precision="mixed"
     is the generator field of (noise_seed, request_event(request seed)); its
     coarse part draws the restriction of that field."""
     import torch
-    from . import g_unit_variance
+    from . import coarsen_transfer_host, g_unit_variance
     from workloads import serve_mesh
     device = torch.device(device or "cuda:0")
     kappa = 1.0 / corr_len
@@ -394,13 +405,18 @@ def build_gpu_server(levels=(32, 64, 128, 256), corr_len=0.05, precision="mixed"
     slots = slots or {n: default_slots.get(n, 8) for n in sizes}
     engines = {}
     meshes = {n: serve_mesh(n) for n in levels}
-    for n in sizes:
-        need = {}
-        if n in levels:
-            need[n] = meshes[n]
+    # finest first: the coarse part of level n projects with Pi of the (n/2)^3 box
+    # onto level n's mesh, coarsened from the fine engine's Pi (children summed,
+    # eq. recursive_l2_projection) instead of clipped again
+    for n in sorted(sizes, reverse=True):
+        need = {n: meshes[n]} if n in levels else {}
+        coarse = {}
         if 2 * n in levels:
-            need[2 * n] = meshes[2 * n]
-        engines[n] = GpuEngine(n, kappa, g, precision, slots[n], device, meshes=need, poll=poll)
+            coarse[2 * n] = coarsen_transfer_host(2 * n, *engines[2 * n].host_transfers[2 * n])
+        engines[n] = GpuEngine(n, kappa, g, precision, slots[n], device, meshes=need, poll=poll,
+                               transfers=coarse)
+        if 2 * n in engines:
+            engines[2 * n].host_transfers.clear()     # device copies are registered
     if hbm_budget is None:
         hbm_budget = sum(e.slot_bytes * e.slots for e in engines.values()) + (8 << 30)
 

@@ -7,6 +7,7 @@ import subprocess
 import sys
 
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 from oracle import transfer as T
@@ -140,6 +141,46 @@ def test_host_transfer_matches_oracle(lib, name, rows):
         ref = dict(zip(c_or.tolist(), v_or.tolist()))
         for k in set(got) | set(ref):
             assert abs(got.get(k, 0.0) - ref.get(k, 0.0)) <= 1e-12, (r, k)
+
+
+@pytest.mark.parametrize("name,rows", [("box16", 200), ("box64", 40)])
+def test_coarsened_transfer_matches_oracle_on_coarse_box(lib, name, rows):
+    """Pi of the (n/2)^3 box from Pi of the n^3 box (children summed) against the
+    oracle's geometric overlaps on the coarse box (eq. recursive_l2_projection)."""
+    import paper_1712_06758_amd as P
+    w = WORKLOADS[name]
+    xyz, tets = w.mesh()
+    rp, ci, cv = P.build_transfer_host(w.n, xyz, tets)
+    rc, cc, vc = P.coarsen_transfer_host(w.n, rp, ci, cv)
+    assert rc.shape == rp.shape and rc[0] == 0 and rc[-1] == cc.size <= ci.size
+    np.testing.assert_allclose(np.add.reduceat(vc, rc[:-1]), 1.0, atol=1e-12)
+    m = w.n // 2
+    assert cc.min() >= 0 and cc.max() < m ** 3
+    sel = np.random.default_rng(2).choice(tets.shape[0], rows, replace=False)
+    for r in sel:
+        assert np.all(np.diff(cc[rc[r]:rc[r + 1]]) > 0)
+        c_or, v_or = T.tet_row(xyz, tets[r], m)
+        got = dict(zip(cc[rc[r]:rc[r + 1]].tolist(), vc[rc[r]:rc[r + 1]].tolist()))
+        ref = dict(zip(c_or.tolist(), v_or.tolist()))
+        for k in set(got) | set(ref):
+            assert abs(got.get(k, 0.0) - ref.get(k, 0.0)) <= 1e-12, (r, k)
+    # and against the library's own clipper run on the coarse box
+    rg, cg, vg = P.build_transfer_host(m, xyz, tets)
+    A = sp.csr_matrix((vc, cc, rc), shape=(tets.shape[0], m ** 3))
+    B = sp.csr_matrix((vg, cg, rg), shape=(tets.shape[0], m ** 3))
+    assert abs(A - B).max() <= 1e-12
+
+
+def test_coarsen_transfer_rejects_bad_input(lib):
+    import paper_1712_06758_amd as P
+    rp = np.array([0, 2], dtype=np.int64)
+    with pytest.raises(P.SpdeError):
+        P.coarsen_transfer_host(8, rp, np.array([0, 512], dtype=np.int32), np.array([0.5, 0.5]))
+    with pytest.raises(P.SpdeError):
+        P.coarsen_transfer_host(7, rp, np.array([0, 1], dtype=np.int32), np.array([0.5, 0.5]))
+    with pytest.raises(P.SpdeError):
+        P.coarsen_transfer_host(8, np.array([0, 2, 1], dtype=np.int64), np.array([0, 1], dtype=np.int32),
+                                np.array([0.5, 0.5]))
 
 
 def test_host_transfer_aligned_mesh_is_injection(lib):
