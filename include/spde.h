@@ -344,10 +344,15 @@ spde_status spde_get_tiles(spde_handle h, int level, int* down_shape, int* up_sh
 /* Iterations per convergence poll (default 8; 1..256). */
 spde_status spde_set_poll_interval(spde_handle h, int iters);
 
-/* Per-kernel timing with HIP events on the sampling stream.  While enabled,
- * kernels are launched one by one (no graphs) with an event pair around each
- * launch of the named kernel classes; accumulated times are read with
- * spde_timing_get().  enable = 0 stops and keeps the totals; -1 clears. */
+/* Per-kernel timing with HIP events on the sampling stream; accumulated times
+ * and algorithmic bytes are read with spde_timing_get().
+ *   enable = 1: every kernel class; kernels are launched one by one (no
+ *               graphs) with an event pair around each launch.
+ *   enable = 2: the operator pass only: per iteration the other kernels
+ *               replay as one captured graph and the operator launch between
+ *               the replays carries the event pair (graphs stay on).
+ *   enable = 0 stops and keeps the totals; -1 clears the totals (the mode
+ *   is kept). */
 spde_status spde_timing(spde_handle h, int enable);
 int         spde_kernel_count(void);
 const char* spde_kernel_name(int id);

@@ -121,8 +121,12 @@ struct Ctx {
   bool tuned = false;
   bool autotune = true;
   int face_precond = 1;          // 0 diag(M)^-1, 1 truncated Neumann series of M^-1
-  // timing
-  bool timing = false;
+  // timing: 0 off; 1 every kernel class, plain launches; 2 the operator pass
+  // only: each iteration's other kernels replay as a one-iteration graph and
+  // the operator launch between them is bracketed by an event pair
+  int timing = 0;
+  std::map<int64_t, hipGraphExec_t> graphs_v;   // (first slot, batch) -> one iteration without the operator
+  bool capturing = false;                       // no event pairs inside a captured graph
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<LaunchRec> recs;
@@ -231,20 +235,20 @@ struct Timed {
   int kid, iter, level, s0, nslots;
   hipStream_t st;
   hipEvent_t e0 = nullptr;
+  bool on = false;
   Timed(Ctx* c_, int kid_, int iter_, hipStream_t st_, int level_ = 0, int s0_ = 0, int nslots_ = -1)
       : c(c_), kid(kid_), iter(iter_), level(level_), s0(s0_), nslots(nslots_), st(st_) {
-    if (c->timing) {
-      e0 = next_event(c);
-      if (e0) hipEventRecord(e0, st);
-    }
+    on = !c->capturing && (c->timing == 1 || (c->timing == 2 && kid == KID_OPERATOR));
+    if (!on) return;
+    e0 = next_event(c);
+    if (e0) hipEventRecord(e0, st);
   }
   ~Timed() {
-    if (c->timing && e0) {
-      hipEvent_t e1 = next_event(c);
-      if (e1) {
-        hipEventRecord(e1, st);
-        c->recs.push_back({kid, iter, level, s0, nslots, e0, e1});
-      }
+    if (!on || !e0) return;
+    hipEvent_t e1 = next_event(c);
+    if (e1) {
+      hipEventRecord(e1, st);
+      c->recs.push_back({kid, iter, level, s0, nslots, e0, e1});
     }
   }
 };
@@ -342,29 +346,44 @@ spde_status enqueue_vcycle(Ctx* c, const View& V, int batch, hipStream_t st, int
   return SPDE_OK;
 }
 
-spde_status enqueue_iteration(Ctx* c, const View& V, int batch, hipStream_t st, int iter) {
+// One MINRES iteration without its operator pass: V-cycle and scalars.
+spde_status enqueue_vpart(Ctx* c, const View& V, int batch, hipStream_t st, int iter) {
   spde_status s = enqueue_vcycle(c, V, batch, st, iter, V.F.vu[0], V.F.vu[1], V.F.z[0], V.F.z[1], V.F.sc,
                                  V.F.part_up);
   if (s != SPDE_OK) return s;
-  {
-    Timed t(c, KID_SCALAR, iter, st, 0, V.s0, batch);
-    HIPCHK(launch_scalar(V.F, tiles_for(c->shape_up[0], c->n), c->nb_pb, batch, st));
-  }
-  {
-    Timed t(c, KID_OPERATOR, iter, st, 0, V.s0, batch);
-    HIPCHK(launch_operator(c->fp64(), V.F, c->box, batch, st));
-  }
+  Timed t(c, KID_SCALAR, iter, st, 0, V.s0, batch);
+  HIPCHK(launch_scalar(V.F, tiles_for(c->shape_up[0], c->n), c->nb_pb, batch, st));
   return SPDE_OK;
 }
 
-spde_status get_graph(Ctx* c, const View& V, int batch, hipStream_t st, hipGraphExec_t* out) {
+spde_status enqueue_operator(Ctx* c, const View& V, int batch, hipStream_t st, int iter) {
+  Timed t(c, KID_OPERATOR, iter, st, 0, V.s0, batch);
+  HIPCHK(launch_operator(c->fp64(), V.F, c->box, batch, st));
+  return SPDE_OK;
+}
+
+spde_status enqueue_iteration(Ctx* c, const View& V, int batch, hipStream_t st, int iter) {
+  spde_status s = enqueue_vpart(c, V, batch, st, iter);
+  if (s != SPDE_OK) return s;
+  return enqueue_operator(c, V, batch, st, iter);
+}
+
+// K-iteration graph (vpart_only: one iteration without its operator pass),
+// captured on first use for the slots of V.
+spde_status get_graph(Ctx* c, const View& V, int batch, hipStream_t st, hipGraphExec_t* out,
+                      bool vpart_only = false) {
   const int64_t key = ((int64_t)V.s0 << 32) | (int64_t)batch;
-  auto it = c->graphs.find(key);
-  if (it != c->graphs.end()) { *out = it->second; return SPDE_OK; }
+  auto& tab = vpart_only ? c->graphs_v : c->graphs;
+  auto it = tab.find(key);
+  if (it != tab.end()) { *out = it->second; return SPDE_OK; }
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;
   spde_status s = SPDE_OK;
-  for (int k = 0; k < c->poll && s == SPDE_OK; ++k) s = enqueue_iteration(c, V, batch, st, 0);
+  if (vpart_only) s = enqueue_vpart(c, V, batch, st, 0);
+  else
+    for (int k = 0; k < c->poll && s == SPDE_OK; ++k) s = enqueue_iteration(c, V, batch, st, 0);
+  c->capturing = false;
   hipError_t e = hipStreamEndCapture(st, &g);
   if (s != SPDE_OK) { if (g) hipGraphDestroy(g); return s; }
   if (e != hipSuccess) return fail(SPDE_EHIP, "graph capture: %s", hipGetErrorString(e));
@@ -372,7 +391,7 @@ spde_status get_graph(Ctx* c, const View& V, int batch, hipStream_t st, hipGraph
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   if (e != hipSuccess) return fail(SPDE_EHIP, "graph instantiate: %s", hipGetErrorString(e));
-  c->graphs[key] = ex;
+  tab[key] = ex;
   *out = ex;
   return SPDE_OK;
 }
@@ -381,7 +400,24 @@ spde_status get_graph(Ctx* c, const View& V, int batch, hipStream_t st, hipGraph
 // and count is the poll interval, else plain launches.
 spde_status enqueue_block(Ctx* c, const View& V, int batch, hipStream_t st, bool graphs, int iter0, int count) {
   hipGraphExec_t ex = nullptr;
-  if (graphs && count == c->poll && get_graph(c, V, batch, st, &ex) != SPDE_OK) {
+  if (graphs && c->timing == 2) {
+    // timing of the operator pass: per iteration, the rest replays as a graph
+    // and the operator launch between the replays carries the event pair
+    if (get_graph(c, V, batch, st, &ex, true) != SPDE_OK) {
+      hipGetLastError();
+      c->use_graphs = false;
+      ex = nullptr;
+    }
+    if (ex) {
+      for (int k = 0; k < count; ++k) {
+        HIPCHK(hipGraphLaunch(ex, st));
+        spde_status s = enqueue_operator(c, V, batch, st, iter0 + k + 1);
+        if (s != SPDE_OK) return s;
+      }
+      return SPDE_OK;
+    }
+  }
+  if (graphs && c->timing == 0 && count == c->poll && get_graph(c, V, batch, st, &ex) != SPDE_OK) {
     // capture not available on this stream: fall back to plain launches
     hipGetLastError();
     c->use_graphs = false;
@@ -401,6 +437,8 @@ spde_status enqueue_block(Ctx* c, const View& V, int batch, hipStream_t st, bool
 void drop_graphs(Ctx* c) {
   for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
   c->graphs.clear();
+  for (auto& kv : c->graphs_v) hipGraphExecDestroy(kv.second);
+  c->graphs_v.clear();
 }
 
 spde_status check_ready(Ctx* c) {
@@ -805,7 +843,7 @@ spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_de
       HIPCHK(launch_init_gen(c->F, bx, src.seed, src.event0, src.coupled, scale, batch, c->rtol, c->max_iter, 0,
                              st));
   }
-  const bool graphs = c->use_graphs && !c->timing && st != nullptr;
+  const bool graphs = c->use_graphs && c->timing != 1 && st != nullptr;
   // A batch of 8 or more runs as two halves on two streams, so that the
   // memory-bound operator pass of one half can overlap the compute-bound
   // V-cycle of the other and each fills the other's launch tails.  The halves
@@ -988,7 +1026,7 @@ spde_status spde_slots_step(spde_handle h, int nslots, int iters, void* stream) 
   if (iters < 1) return fail(SPDE_EINVAL, "iters must be >= 1");
   HIPCHK(hipSetDevice(c->device));
   hipStream_t st = pick_stream(c, stream);
-  const bool graphs = c->use_graphs && !c->timing && st != nullptr;
+  const bool graphs = c->use_graphs && c->timing != 1 && st != nullptr;
   int done = 0;
   const View V0 = make_view(c, 0);
   while (done < iters) {
@@ -1211,12 +1249,12 @@ spde_status spde_set_poll_interval(spde_handle h, int iters) {
 spde_status spde_timing(spde_handle h, int enable) {
   Ctx* c = reinterpret_cast<Ctx*>(h);
   if (!c) return fail(SPDE_EINVAL, "null handle");
-  if (enable < 0) {
+  if (enable < -1 || enable > 2) return fail(SPDE_EINVAL, "timing mode must be -1, 0, 1 or 2");
+  if (enable < 0) {   // clear the totals, keep the mode
     for (int k = 0; k < KID_COUNT; ++k) { c->t_ms[k] = 0; c->t_n[k] = 0; c->t_bytes[k] = 0; }
-    c->timing = false;
     return SPDE_OK;
   }
-  c->timing = enable != 0;
+  c->timing = enable;
   return SPDE_OK;
 }
 
