@@ -288,3 +288,31 @@ def test_edge_cases(torch_cuda):
     u = box.sample(torch.tensor(xi, device="cuda"), u_box=True)["u_box"].cpu().numpy()
     ref = oracle_u(32, 20.0, gval(20.0), xi)
     assert max(rel_l2(u[b], ref[b]) for b in range(7)) <= 1e-7
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_timing_modes_do_not_change_results(torch_cuda, mode):
+    """Timed calls (every kernel with plain launches, or the operator between
+    one-iteration graph replays) give bitwise the untimed fields, and the
+    operator's launches and algorithmic bytes are recorded."""
+    torch = torch_cuda
+    say(f"timing mode {mode} n=32")
+    n, kappa = 32, 20.0
+    xi = torch.tensor(xi_batch(n, [21, 22, 23]), device="cuda")
+    box = P().Box(n, kappa, precision="mixed", max_batch=3)
+    ref = box.sample(xi, u_box=True)
+    box.timing(mode)
+    box.timing(-1)
+    out = box.sample(xi, u_box=True)
+    box.timing(0)
+    rep = box.timing_report()
+    torch.cuda.synchronize()
+    assert torch.equal(ref["u_box"], out["u_box"])
+    assert ref["iters"].tolist() == out["iters"].tolist()
+    op = rep["operator"]
+    assert op["launches"] == int(out["iters"].max()) + 1
+    assert op["bytes_per_launch"] > 0 and op["total_ms"] > 0
+    if mode == 2:
+        assert set(k for k, v in rep.items() if v["launches"]) == {"operator"}
+    else:
+        assert rep["mg_up_fine"]["launches"] > 0
