@@ -81,6 +81,15 @@ struct Box {
   double h15;        // h^{3/2}
 };
 
+#ifdef __HIPCC__
+// Byte-offset load from a uniform base (global_load with a scalar base and a
+// 32-bit lane offset).
+template <typename T>
+__device__ __forceinline__ T ld_off(const T* base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+#endif
+
 // kappa^2 h^3 of cell c (same rounding as the host's kappa * kappa * h^3).
 // VAR: cell-wise kappa (a compile-time choice in the hot kernels, so that the
 // constant path carries no branch); the run-time form serves the others.

@@ -1168,6 +1168,106 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
   if (wm >= 1) x_update(wj, wm >= 2 ? wjm1 : 0.0);
 }
 
+// Column form of the operator pass for n a multiple of 64.  A block owns
+// 64 x 4 cell columns (one grid row per wave) and walks ZC planes up z.  The
+// z-window of the z faces slides in registers (one new plane per step instead
+// of seven loads), and the z neighbour of zhat is the previous step's value;
+// the x and y windows are loaded as in k_operator.  Same arithmetic, in the
+// same order, as k_operator.
+template <typename TZ, int POLY, bool VAR, int ZC>
+__global__ __launch_bounds__(kBlock) void k_operator_col(Fields F, Box bx, int nb) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int slot = lb / nb, t = lb - slot * nb;
+  const Scalars* S = F.sc + slot;
+  const int state = S->state;
+  if (state != ST_ACTIVE && state != ST_FINISH) return;
+  const int j = S->pit;
+  const int p = j & 1, pq = p ^ 1;
+  const int64_t nc = bx.nc;
+  const int n = bx.n;
+  const int64_t n2 = bx.n2;
+  const int tpx = n >> 6, tpy = n >> 2;
+  const int x0 = (t % tpx) << 6, y0 = ((t / tpx) % tpy) << 2, z0 = (t / (tpx * tpy)) * ZC;
+  const int i = x0 + (int)(threadIdx.x & 63);
+  const int jj = __builtin_amdgcn_readfirstlane(y0 + (int)(threadIdx.x >> 6));
+  const int64_t col = i + (int64_t)n * jj;
+  const int64_t co = cell_off(slot, nc);
+  const bool active = state == ST_ACTIVE;
+  const bool has_prev = j > 1;
+  const int wm = S->wmode;
+  const bool upd_x = wm >= 1 && ((j & 1) == 0 || state == ST_FINISH);
+  const double zs = S->zs, av = S->a_v, bv = S->b_v;
+  const double sww = S->ww, swwp = S->ww_prev, sxw = S->xw, sxp = S->xpend;
+  auto x_update = [&](int64_t c, double wj, double wjm1) {
+    if (upd_x) {
+      const double inc = sxp * wjm1 + sxw * wj;
+      F.x[co + c] = j == 2 ? inc : F.x[co + c] + inc;
+    }
+  };
+  if (!active) {
+    for (int kk = 0; kk < ZC; ++kk) {
+      const int64_t c = col + n2 * (z0 + kk);
+      x_update(c, F.w[pq][co + c], wm >= 2 ? F.w[p][co + c] : 0.0);
+    }
+    return;
+  }
+  const TZ* z = reinterpret_cast<const TZ*>(F.z[p]) + co;
+  const double* vz = F.vs[p] + face_off(slot, 2, nc) + col;
+  // z face of plane g of this column, odd reflection about the boundary faces
+  // 0 and n (the plane index is block-uniform, so the reflection is scalar)
+  auto face_z = [&](int g) {
+    const bool neg = g < 0 || g > n;
+    const int src = g < 0 ? -g : (g > n ? 2 * n - g : g);
+    const double x = vz[n2 * min(src, n - 1)];
+    return x * (src == n ? 0.0 : (neg ? -1.0 : 1.0));
+  };
+  double wz[7];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) wz[q] = face_z(z0 - 3 + q);
+  double zprev = (double)z[col + n2 * max(z0 - 1, 0)];
+  for (int kk = 0; kk < ZC; ++kk) {
+    const int k = z0 + kk;
+    const int64_t c = col + n2 * k;
+    wz[6] = face_z(k + 3);
+    double w[2][7], vo[3];
+    const double zc = (double)z[c];
+    line_load_ext<3>(F.vs[p] + face_off(slot, 0, nc), c, 1, i, n, w[0]);
+    line_load_ext<3>(F.vs[p] + face_off(slot, 1, nc), c, n, jj, n, w[1]);
+    const double zlo[3] = {(double)z[i > 0 ? c - 1 : c], (double)z[jj > 0 ? c - n : c], k > 0 ? zprev : zc};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) vo[d] = F.vs[pq][face_off(slot, d, nc) + c];
+    const double vuc = F.vu[p][co + c], vuo = F.vu[pq][co + c];
+    const double wj = F.w[pq][co + c], wjm1 = F.w[p][co + c];
+    const double kc = VAR ? bx.kap[c] : 0.0;
+    const int idx[3] = {i, jj, k};
+    double dv = 0.0, nf[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double* wd = d == 2 ? wz : w[d];
+      double mz, zf, zh;
+      line_terms_ext(wd, POLY, mz, zf, zh);
+      dv += zh - zf;
+      const double a = zs * (mz + bx.h2 * (zlo[d] - zc));
+      const double nv = a - av * wd[3];
+      nf[d] = idx[d] > 0 ? (has_prev ? nv - bv * vo[d] : nv) : 0.0;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) F.vs[pq][face_off(slot, d, nc) + c] = nf[d];
+    const double k2 = VAR ? (kc * kc) * bx.h3 : bx.k2h3;
+    const double Au = zs * (bx.h2q * dv - k2 * zc);
+    const double nu = Au - av * vuc;
+    F.vu[pq][co + c] = has_prev ? nu - bv * vuo : nu;
+    double wn = zs * zc;
+    if (wm >= 1) wn += sww * wj;
+    if (wm >= 2) wn += swwp * wjm1;
+    F.w[p][co + c] = wm >= 0 ? wn : wjm1;
+    if (wm >= 1) x_update(c, wj, wm >= 2 ? wjm1 : 0.0);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) wz[q] = wz[q + 1];
+    zprev = zc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // finishing
 

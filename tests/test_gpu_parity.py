@@ -25,7 +25,7 @@ def P():
     return P_
 
 
-@pytest.mark.parametrize("n,batch", [(4, 1), (8, 3), (16, 2)])
+@pytest.mark.parametrize("n,batch", [(4, 1), (8, 3), (16, 2), (64, 2)])
 def test_operator_matches_oracle_matrix(torch_cuda, n, batch):
     torch = torch_cuda
     say(f"operator n={n} batch={batch}")

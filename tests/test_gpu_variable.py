@@ -44,7 +44,7 @@ def test_constant_fields_equal_constant_path_bitwise(torch_cuda, prec):
     assert np.array_equal(a["relres"], b["relres"])
 
 
-@pytest.mark.parametrize("n", [8, 16])
+@pytest.mark.parametrize("n", [8, 16, 64])
 def test_operator_with_cell_kappa_matches_oracle(torch_cuda, n):
     say(f"variable operator n={n}")
     torch = torch_cuda
