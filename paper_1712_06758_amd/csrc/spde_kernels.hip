@@ -1170,12 +1170,17 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
 
 // Column form of the operator pass for n a multiple of 64.  A block owns
 // 64 x 4 cell columns (one grid row per wave) and walks ZC planes up z.  The
-// z-window of the z faces slides in registers (one new plane per step instead
-// of seven loads), and the z neighbour of zhat is the previous step's value;
-// the x and y windows are loaded as in k_operator.  Same arithmetic, in the
-// same order, as k_operator.
+// z-window of the z faces slides in registers (one new plane per step), the z
+// neighbour of zhat is the previous step's value, and each step stages the x
+// faces of its 4 rows (with a 3-face halo along x) and the y faces of rows
+// -3 .. +6 in LDS, from which the x and y windows are read.  Same arithmetic,
+// in the same order, as k_operator.
 template <typename TZ, int POLY, bool VAR, int ZC>
 __global__ __launch_bounds__(kBlock) void k_operator_col(Fields F, Box bx, int nb) {
+  constexpr int XW = 64 + 6, AXF = XW * 4, RXF = (AXF + kBlock - 1) / kBlock;   // x faces, halo 3 in x
+  constexpr int AYF = 64 * (4 + 6), RYF = (AYF + kBlock - 1) / kBlock;           // y faces, halo 3 in y
+  __shared__ double sxf[2][AXF];
+  __shared__ double syf[2][AYF];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int slot = lb / nb, t = lb - slot * nb;
   const Scalars* S = F.sc + slot;
@@ -1188,8 +1193,9 @@ __global__ __launch_bounds__(kBlock) void k_operator_col(Fields F, Box bx, int n
   const int64_t n2 = bx.n2;
   const int tpx = n >> 6, tpy = n >> 2;
   const int x0 = (t % tpx) << 6, y0 = ((t / tpx) % tpy) << 2, z0 = (t / (tpx * tpy)) * ZC;
-  const int i = x0 + (int)(threadIdx.x & 63);
-  const int jj = __builtin_amdgcn_readfirstlane(y0 + (int)(threadIdx.x >> 6));
+  const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int i = x0 + lane;
+  const int jj = __builtin_amdgcn_readfirstlane(y0 + wv);
   const int64_t col = i + (int64_t)n * jj;
   const int64_t co = cell_off(slot, nc);
   const bool active = state == ST_ACTIVE;
@@ -1211,7 +1217,30 @@ __global__ __launch_bounds__(kBlock) void k_operator_col(Fields F, Box bx, int n
     }
     return;
   }
+  // staged items: byte offset within a plane and the odd-reflection factor
+  uint32_t xo[RXF], yo[RYF];
+  double xf[RXF], yf[RYF];
+#pragma unroll
+  for (int r = 0; r < RXF; ++r) {
+    const int q = tid + r * kBlock;
+    const int gx = x0 + q % XW - 3, gy = y0 + q / XW;
+    const bool neg = gx < 0 || gx > n;
+    const int src = gx < 0 ? -gx : (gx > n ? 2 * n - gx : gx);
+    xo[r] = q < AXF ? (uint32_t)(min(src, n - 1) + n * gy) * 8u : 0u;
+    xf[r] = (q >= AXF || src == n) ? 0.0 : (neg ? -1.0 : 1.0);
+  }
+#pragma unroll
+  for (int r = 0; r < RYF; ++r) {
+    const int q = tid + r * kBlock;
+    const int gx = x0 + q % 64, gy = y0 + q / 64 - 3;
+    const bool neg = gy < 0 || gy > n;
+    const int src = gy < 0 ? -gy : (gy > n ? 2 * n - gy : gy);
+    yo[r] = q < AYF ? (uint32_t)(gx + n * min(src, n - 1)) * 8u : 0u;
+    yf[r] = (q >= AYF || src == n) ? 0.0 : (neg ? -1.0 : 1.0);
+  }
   const TZ* z = reinterpret_cast<const TZ*>(F.z[p]) + co;
+  const double* vs0 = F.vs[p] + face_off(slot, 0, nc);
+  const double* vs1 = F.vs[p] + face_off(slot, 1, nc);
   const double* vz = F.vs[p] + face_off(slot, 2, nc) + col;
   // z face of plane g of this column, odd reflection about the boundary faces
   // 0 and n (the plane index is block-uniform, so the reflection is scalar)
@@ -1227,18 +1256,39 @@ __global__ __launch_bounds__(kBlock) void k_operator_col(Fields F, Box bx, int n
   double zprev = (double)z[col + n2 * max(z0 - 1, 0)];
   for (int kk = 0; kk < ZC; ++kk) {
     const int k = z0 + kk;
-    const int64_t c = col + n2 * k;
+    const int64_t pk = n2 * k;
+    const int64_t c = col + pk;
+    const int b = kk & 1;
+    // stage this plane's x and y faces (the buffer written two steps ago has
+    // been read by everyone: the previous step's barrier lies between)
+    const double* px = vs0 + pk;
+    const double* py = vs1 + pk;
+#pragma unroll
+    for (int r = 0; r < RXF; ++r) {
+      const int q = tid + r * kBlock;
+      if ((r + 1) * kBlock <= AXF || q < AXF) sxf[b][q] = ld_off(px, xo[r]) * xf[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RYF; ++r) {
+      const int q = tid + r * kBlock;
+      if ((r + 1) * kBlock <= AYF || q < AYF) syf[b][q] = ld_off(py, yo[r]) * yf[r];
+    }
     wz[6] = face_z(k + 3);
-    double w[2][7], vo[3];
+    double vo[3];
     const double zc = (double)z[c];
-    line_load_ext<3>(F.vs[p] + face_off(slot, 0, nc), c, 1, i, n, w[0]);
-    line_load_ext<3>(F.vs[p] + face_off(slot, 1, nc), c, n, jj, n, w[1]);
     const double zlo[3] = {(double)z[i > 0 ? c - 1 : c], (double)z[jj > 0 ? c - n : c], k > 0 ? zprev : zc};
 #pragma unroll
     for (int d = 0; d < 3; ++d) vo[d] = F.vs[pq][face_off(slot, d, nc) + c];
     const double vuc = F.vu[p][co + c], vuo = F.vu[pq][co + c];
     const double wj = F.w[pq][co + c], wjm1 = F.w[p][co + c];
     const double kc = VAR ? bx.kap[c] : 0.0;
+    __syncthreads();
+    double w[2][7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      w[0][q] = sxf[b][lane + q + XW * wv];
+      w[1][q] = syf[b][lane + 64 * (wv + q)];
+    }
     const int idx[3] = {i, jj, k};
     double dv = 0.0, nf[3];
 #pragma unroll
