@@ -348,9 +348,9 @@ spde_status spde_set_poll_interval(spde_handle h, int iters);
  * and algorithmic bytes are read with spde_timing_get().
  *   enable = 1: every kernel class; kernels are launched one by one (no
  *               graphs) with an event pair around each launch.
- *   enable = 2: the operator pass only: per iteration the other kernels
- *               replay as one captured graph and the operator launch between
- *               the replays carries the event pair (graphs stay on).
+ *   enable = 2: the operator pass only: in each poll block the passes
+ *               0, 3, 6, ... run on their own, bracketed by an event pair,
+ *               and everything between them replays as captured graphs.
  *   enable = 0 stops and keeps the totals; -1 clears the totals (the mode
  *   is kept). */
 spde_status spde_timing(spde_handle h, int enable);

@@ -115,17 +115,16 @@ struct Ctx {
   // execution
   bool use_graphs = true;
   int poll = 8;
-  std::map<int64_t, hipGraphExec_t> graphs;   // (first slot, batch) -> K-iteration graph
+  std::map<int64_t, hipGraphExec_t> graphs;   // (first slot, half-iterations, batch) -> graph
   int split = 1;                 // 2: batches of 8+ run as two halves on two streams
   int expect_iters = 0;          // iterations (incl. the finishing pass) the last call needed
   bool tuned = false;
   bool autotune = true;
   int face_precond = 1;          // 0 diag(M)^-1, 1 truncated Neumann series of M^-1
   // timing: 0 off; 1 every kernel class, plain launches; 2 the operator pass
-  // only: each iteration's other kernels replay as a one-iteration graph and
-  // the operator launch between them is bracketed by an event pair
+  // only: every third operator launch runs on its own between graph replays,
+  // bracketed by an event pair
   int timing = 0;
-  std::map<int64_t, hipGraphExec_t> graphs_v;   // (first slot, batch) -> one iteration without the operator
   bool capturing = false;                       // no event pairs inside a captured graph
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
@@ -368,21 +367,20 @@ spde_status enqueue_iteration(Ctx* c, const View& V, int batch, hipStream_t st, 
   return enqueue_operator(c, V, batch, st, iter);
 }
 
-// K-iteration graph (vpart_only: one iteration without its operator pass),
-// captured on first use for the slots of V.
-spde_status get_graph(Ctx* c, const View& V, int batch, hipStream_t st, hipGraphExec_t* out,
-                      bool vpart_only = false) {
-  const int64_t key = ((int64_t)V.s0 << 32) | (int64_t)batch;
-  auto& tab = vpart_only ? c->graphs_v : c->graphs;
-  auto it = tab.find(key);
-  if (it != tab.end()) { *out = it->second; return SPDE_OK; }
+// Graph of L half-iterations for the slots of V, captured on first use:
+// V-part, operator, V-part, ... (L = 2 K is K whole iterations; L odd ends
+// with a V-part).  The iteration numbers inside a graph are irrelevant: the
+// kernels take their state from the per-slot scalars.
+spde_status get_graph(Ctx* c, const View& V, int batch, hipStream_t st, hipGraphExec_t* out, int L) {
+  const int64_t key = ((int64_t)V.s0 << 40) | ((int64_t)L << 24) | (int64_t)batch;
+  auto it = c->graphs.find(key);
+  if (it != c->graphs.end()) { *out = it->second; return SPDE_OK; }
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   c->capturing = true;
   spde_status s = SPDE_OK;
-  if (vpart_only) s = enqueue_vpart(c, V, batch, st, 0);
-  else
-    for (int k = 0; k < c->poll && s == SPDE_OK; ++k) s = enqueue_iteration(c, V, batch, st, 0);
+  for (int h = 0; h < L && s == SPDE_OK; ++h)
+    s = (h & 1) ? enqueue_operator(c, V, batch, st, 0) : enqueue_vpart(c, V, batch, st, 0);
   c->capturing = false;
   hipError_t e = hipStreamEndCapture(st, &g);
   if (s != SPDE_OK) { if (g) hipGraphDestroy(g); return s; }
@@ -391,41 +389,46 @@ spde_status get_graph(Ctx* c, const View& V, int batch, hipStream_t st, hipGraph
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   if (e != hipSuccess) return fail(SPDE_EHIP, "graph instantiate: %s", hipGetErrorString(e));
-  tab[key] = ex;
+  c->graphs[key] = ex;
   *out = ex;
   return SPDE_OK;
 }
 
-// `count` iterations for the slots of V: a captured graph if graphs are on
-// and count is the poll interval, else plain launches.
-spde_status enqueue_block(Ctx* c, const View& V, int batch, hipStream_t st, bool graphs, int iter0, int count) {
+// Launch the graph of L half-iterations; false if graphs are not available.
+bool launch_graph(Ctx* c, const View& V, int batch, hipStream_t st, int L) {
   hipGraphExec_t ex = nullptr;
-  if (graphs && c->timing == 2) {
-    // timing of the operator pass: per iteration, the rest replays as a graph
-    // and the operator launch between the replays carries the event pair
-    if (get_graph(c, V, batch, st, &ex, true) != SPDE_OK) {
-      hipGetLastError();
-      c->use_graphs = false;
-      ex = nullptr;
-    }
-    if (ex) {
-      for (int k = 0; k < count; ++k) {
-        HIPCHK(hipGraphLaunch(ex, st));
-        spde_status s = enqueue_operator(c, V, batch, st, iter0 + k + 1);
-        if (s != SPDE_OK) return s;
-      }
-      return SPDE_OK;
-    }
-  }
-  if (graphs && c->timing == 0 && count == c->poll && get_graph(c, V, batch, st, &ex) != SPDE_OK) {
-    // capture not available on this stream: fall back to plain launches
+  if (get_graph(c, V, batch, st, &ex, L) != SPDE_OK || !ex) {
     hipGetLastError();
     c->use_graphs = false;
-    ex = nullptr;
+    return false;
   }
-  if (ex) {
-    HIPCHK(hipGraphLaunch(ex, st));
-    return SPDE_OK;
+  return hipGraphLaunch(ex, st) == hipSuccess;
+}
+
+// Operator passes timed in mode 2: every kTimedStride-th iteration of a block
+// (both parities of the iteration number occur).
+constexpr int kTimedStride = 3;
+
+// `count` iterations for the slots of V: a captured graph if graphs are on
+// and count is the poll interval, else plain launches.  In timing mode 2 the
+// operator passes k = 0, 3, 6, ... of the block are launched on their own,
+// bracketed by an event pair, and everything between them replays as graphs.
+spde_status enqueue_block(Ctx* c, const View& V, int batch, hipStream_t st, bool graphs, int iter0, int count) {
+  if (graphs && c->timing == 2) {
+    bool ok = launch_graph(c, V, batch, st, 1);   // V-part of iteration 0
+    for (int k = 0; ok && k < count; k += kTimedStride) {
+      spde_status s = enqueue_operator(c, V, batch, st, iter0 + k + 1);
+      if (s != SPDE_OK) return s;
+      const int next = k + kTimedStride;
+      // iterations k+1 .. next-1 whole, then the V-part of `next` (or the rest of the block)
+      const int L = next < count ? 2 * (kTimedStride - 1) + 1 : 2 * (count - 1 - k);
+      if (L > 0) ok = launch_graph(c, V, batch, st, L);
+    }
+    if (ok) return SPDE_OK;
+    return fail(SPDE_EHIP, "graph launch failed in timing mode 2");
+  }
+  if (graphs && c->timing == 0 && count == c->poll) {
+    if (launch_graph(c, V, batch, st, 2 * c->poll)) return SPDE_OK;
   }
   for (int k = 0; k < count; ++k) {
     spde_status s = enqueue_iteration(c, V, batch, st, iter0 + k + 1);
@@ -437,8 +440,6 @@ spde_status enqueue_block(Ctx* c, const View& V, int batch, hipStream_t st, bool
 void drop_graphs(Ctx* c) {
   for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
   c->graphs.clear();
-  for (auto& kv : c->graphs_v) hipGraphExecDestroy(kv.second);
-  c->graphs_v.clear();
 }
 
 spde_status check_ready(Ctx* c) {
@@ -1031,7 +1032,7 @@ spde_status spde_slots_step(spde_handle h, int nslots, int iters, void* stream) 
   const View V0 = make_view(c, 0);
   while (done < iters) {
     hipGraphExec_t ex = nullptr;
-    if (graphs && iters - done >= c->poll && get_graph(c, V0, nslots, st, &ex) != SPDE_OK) {
+    if (graphs && iters - done >= c->poll && get_graph(c, V0, nslots, st, &ex, 2 * c->poll) != SPDE_OK) {
       hipGetLastError();
       c->use_graphs = false;
       ex = nullptr;
