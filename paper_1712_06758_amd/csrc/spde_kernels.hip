@@ -837,8 +837,12 @@ __device__ __forceinline__ TM nsum(const TM* v, int x, int y, int z, int m, int 
   return s;
 }
 
+// Threads of the persistent coarse-level kernel (one block per sample; the
+// 16^3 level is its largest, so 1024 threads leave 4 cells per thread).
+constexpr int kCoarseBlock = 1024;
+
 template <typename TM>
-__global__ __launch_bounds__(kBlock) void k_mg_coarse(const TM* __restrict__ btop, TM* __restrict__ etop,
+__global__ __launch_bounds__(kCoarseBlock) void k_mg_coarse(const TM* __restrict__ btop, TM* __restrict__ etop,
                                                       CoarseParams P, const Scalars* __restrict__ sc) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TM* sm = reinterpret_cast<TM*>(smem_raw);
@@ -848,7 +852,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarse(const TM* __restrict__ bto
   const int64_t nc0 = P.lv[0].nc;
   {
     TM* b = sm + P.off[0];
-    for (int c = threadIdx.x; c < nc0; c += kBlock) b[c] = btop[(int64_t)slot * nc0 + c];
+    for (int c = threadIdx.x; c < nc0; c += kCoarseBlock) b[c] = btop[(int64_t)slot * nc0 + c];
   }
   __syncthreads();
   for (int l = 0; l < P.nl - 1; ++l) {
@@ -860,19 +864,19 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarse(const TM* __restrict__ bto
     TM* y = x + nc;
     TM* tt = y + nc;
     const TM k2 = (TM)L.k2, a = (TM)L.a, c0 = (TM)L.c0, c1 = (TM)L.c1, c2 = (TM)L.c2;
-    for (int c = threadIdx.x; c < nc; c += kBlock) {
+    for (int c = threadIdx.x; c < nc; c += kCoarseBlock) {
       const int i = c % m, j = (c / m) % m, k = c / (m * m);
       y[c] = c0 * b[c] / (k2 + a * (TM)nnbr(i, j, k, m));
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < nc; c += kBlock) {
+    for (int c = threadIdx.x; c < nc; c += kCoarseBlock) {
       const int i = c % m, j = (c / m) % m, k = c / (m * m);
       const TM d = k2 + a * (TM)nnbr(i, j, k, m);
       const TM Ay = d * y[c] - a * nsum(y, i, j, k, m, c);
       x[c] = c1 * y[c] + (c2 / d) * (b[c] - Ay);
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < nc; c += kBlock) {
+    for (int c = threadIdx.x; c < nc; c += kCoarseBlock) {
       const int i = c % m, j = (c / m) % m, k = c / (m * m);
       const TM d = k2 + a * (TM)nnbr(i, j, k, m);
       tt[c] = b[c] - (d * x[c] - a * nsum(x, i, j, k, m, c));
@@ -880,7 +884,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarse(const TM* __restrict__ bto
     __syncthreads();
     const int mh = m >> 1;
     TM* bn = sm + P.off[l + 1];
-    for (int C = threadIdx.x; C < mh * mh * mh; C += kBlock) {
+    for (int C = threadIdx.x; C < mh * mh * mh; C += kCoarseBlock) {
       const int I = C % mh, J = (C / mh) % mh, K = C / (mh * mh);
       TM acc = 0;
 #pragma unroll
@@ -899,7 +903,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarse(const TM* __restrict__ bto
     TM* b = sm + P.off[P.nl - 1];
     TM* x = b + nc;
     // coarsest level: a single cell, S~ = kappa^2 H^3 (no neighbours): exact
-    for (int c = threadIdx.x; c < nc; c += kBlock) {
+    for (int c = threadIdx.x; c < nc; c += kCoarseBlock) {
       const int i = c % m, j = (c / m) % m, k = c / (m * m);
       x[c] = b[c] / ((TM)L.k2 + (TM)L.a * (TM)nnbr(i, j, k, m));
     }
@@ -916,12 +920,12 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarse(const TM* __restrict__ bto
     TM* tt = y + nc;
     const TM* xn = sm + P.off[l + 1] + (int)P.lv[l + 1].nc;
     const TM k2 = (TM)L.k2, a = (TM)L.a, c0 = (TM)L.c0, c1 = (TM)L.c1, c2 = (TM)L.c2;
-    for (int c = threadIdx.x; c < nc; c += kBlock) {
+    for (int c = threadIdx.x; c < nc; c += kCoarseBlock) {
       const int i = c % m, j = (c / m) % m, k = c / (m * m);
       x[c] += xn[(i >> 1) + mh * ((j >> 1) + mh * (k >> 1))];
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < nc; c += kBlock) {
+    for (int c = threadIdx.x; c < nc; c += kCoarseBlock) {
       const int i = c % m, j = (c / m) % m, k = c / (m * m);
       const TM d = k2 + a * (TM)nnbr(i, j, k, m);
       const TM r = b[c] - (d * x[c] - a * nsum(x, i, j, k, m, c));
@@ -929,7 +933,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarse(const TM* __restrict__ bto
       y[c] = c0 * r / d;
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < nc; c += kBlock) {
+    for (int c = threadIdx.x; c < nc; c += kCoarseBlock) {
       const int i = c % m, j = (c / m) % m, k = c / (m * m);
       const TM d = k2 + a * (TM)nnbr(i, j, k, m);
       const TM t2 = tt[c] - (d * y[c] - a * nsum(y, i, j, k, m, c));
@@ -939,7 +943,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarse(const TM* __restrict__ bto
   }
   {
     const TM* x = sm + P.off[0] + nc0;
-    for (int c = threadIdx.x; c < nc0; c += kBlock) etop[(int64_t)slot * nc0 + c] = x[c];
+    for (int c = threadIdx.x; c < nc0; c += kCoarseBlock) etop[(int64_t)slot * nc0 + c] = x[c];
   }
   (void)m0;
 }
