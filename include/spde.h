@@ -336,7 +336,7 @@ spde_status spde_set_autotune(spde_handle h, int enable);
  *                              4: 32x4x4  5: 16x8x4  (float64 up-kernels: 1, 4, 5 only)
  *   2.5-D columns x planes:    6: 32x8 x 32  7: 16x16 x 32  8: 32x8 x 16  9: 32x8 x 64
  *   pipelined 2.5-D columns:  10: 32x8 x 32 11: 16x16 x 32 12: 32x8 x 64 13: 16x16 x 64
- *                             14: 32x8 x 128 15: 16x16 x 128
+ *                             14: 32x8 x 128 15: 16x16 x 128 16: 32x8 x 16 17: 16x16 x 16
  * spde_set_tiles fixes the shapes of one level (or all levels with level = -1)
  * and turns autotuning off for the handle; spde_get_tiles reads them. */
 spde_status spde_set_tiles(spde_handle h, int level, int down_shape, int up_shape);

@@ -360,7 +360,7 @@ class Box:
         _abi.check(_abi.lib().spde_set_autotune(self._hh.h, int(bool(enable))))
 
     def set_tiles(self, down: int, up: int, level: int = -1):
-        """Fix the multigrid tile shapes (ids 0..15) of one level or all (-1)."""
+        """Fix the multigrid tile shapes (ids 0..17) of one level or all (-1)."""
         _abi.check(_abi.lib().spde_set_tiles(self._hh.h, int(level), int(down), int(up)))
 
     def get_tiles(self, level: int = 0):

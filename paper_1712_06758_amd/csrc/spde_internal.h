@@ -148,7 +148,7 @@ enum KernelId : int {
 // ---------------------------------------------------------------------------
 // host launchers (defined in spde_kernels.hip)
 namespace spde {
-constexpr int kNumShapes = 16;
+constexpr int kNumShapes = 18;
 extern const int kShapes[kNumShapes][3];
 bool shape_ok_up(int shape, bool fp64);
 bool shape_ok_down(int shape, bool fp64);

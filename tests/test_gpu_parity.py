@@ -213,8 +213,8 @@ def test_every_tile_shape_gives_the_same_vcycle(torch_cuda, prec):
     ref = box.apply_vcycle(r).cpu().numpy()
     rn = r.cpu().numpy()
     tol = 1e-12 if prec == "fp64" else 2e-6
-    ok_up = set(range(16)) if prec == "mixed" else {1, 4, 5} | set(range(6, 16))
-    pairs = [(d, d if d in ok_up else 6) for d in range(16)]
+    ok_up = set(range(18)) if prec == "mixed" else {1, 4, 5} | set(range(6, 18))
+    pairs = [(d, d if d in ok_up else 6) for d in range(18)]
     bad = []
     for d, u in pairs:
         box.set_tiles(d, u)
@@ -230,7 +230,7 @@ def test_every_tile_shape_gives_the_same_vcycle(torch_cuda, prec):
 
 @pytest.mark.parametrize("shape,prec", [(1, "fp64"), (6, "fp64"), (7, "fp64"), (9, "fp64"), (10, "fp64"),
                                         (11, "fp64"), (13, "fp64"), (14, "fp64"), (10, "mixed"), (12, "mixed"),
-                                        (15, "mixed")])
+                                        (15, "mixed"), (17, "mixed"), (16, "fp64")])
 def test_sample_with_tile_shape(torch_cuda, shape, prec):
     torch = torch_cuda
     say(f"sample with tile shape {shape} {prec} n=64")
