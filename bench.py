@@ -82,7 +82,7 @@ def vcycle_gbs(rep):
 
 
 def cpu_baseline(n, kappa, g, xi_np):
-    """The oracle on the machine's host cores: its block-preconditioned MINRES route
+    """The oracle on the host's cores: its block-preconditioned MINRES route
     (the method, with the exact DCT Schur preconditioner, to the same relative
     tolerance as the float64 GPU path) on one noise vector of the workload, and
     its closed-form spectral solve on all of them."""
@@ -149,7 +149,7 @@ def main():
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this sampler runs on one GPU; multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "this sampler runs on one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
