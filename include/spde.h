@@ -126,6 +126,29 @@ spde_status spde_transfer_coarsen(int n_fine, int64_t n_rows, const int64_t* row
                                   int64_t** row_ptr_c, int32_t** col_c, double** val_c,
                                   int64_t* nnz_c);
 
+/* Build the same Pi on the device, bit for bit equal to spde_build_transfer
+ * (the same clipping arithmetic, no fused multiply-adds, the same order of
+ * the pieces).  Two calls, so that the caller allocates every buffer:
+ *   1. spde_build_transfer_device_rows writes the row pointers
+ *      row_ptr_dev [n_tet+1] int64 and returns the entry count in *nnz (host);
+ *      it synchronises `stream`.
+ *   2. The caller allocates col_dev [nnz] int32 and val_dev [nnz] float64;
+ *      spde_build_transfer_device_fill writes them (asynchronous on `stream`),
+ *      given the row_ptr_dev of call 1 and the same mesh.
+ *   n         cells per box edge, in [2, 1024]
+ *   xyz_dev   [n_vert][3] float64 vertex coordinates (device)
+ *   tet_dev   [n_tet][4]  int32 vertex indices (device)
+ * n_vert in [4, 2^31), n_tet in [1, 2^31).  Returns SPDE_EINVAL, naming the
+ * first offending tet, for a vertex index out of range, a vertex outside
+ * [0,1]^3 or a degenerate tet (only vertices that some tet references are
+ * checked); row_ptr_dev is then undefined.  No device memory is allocated. */
+spde_status spde_build_transfer_device_rows(int n, int64_t n_vert, const double* xyz_dev, int64_t n_tet,
+                                            const int32_t* tet_dev, int64_t* row_ptr_dev, int64_t* nnz,
+                                            void* stream);
+spde_status spde_build_transfer_device_fill(int n, int64_t n_vert, const double* xyz_dev, int64_t n_tet,
+                                            const int32_t* tet_dev, const int64_t* row_ptr_dev,
+                                            int32_t* col_dev, double* val_dev, void* stream);
+
 /* Register a device copy of Pi (CSR as produced above).  The arrays are
  * borrowed, not copied: they must stay valid while the handle samples. */
 spde_status spde_set_transfer(spde_handle h, int64_t n_tet, int64_t nnz,

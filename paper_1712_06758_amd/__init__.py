@@ -96,6 +96,33 @@ def build_transfer_host(n: int, xyz: np.ndarray, tets: np.ndarray):
     return row_ptr, cols, vals
 
 
+def build_transfer_device(n: int, xyz, tets, device=None):
+    """Pi = W_h^-1 G built on the GPU by the library's device clipper, equal bit
+    for bit to build_transfer_host.  xyz [n_vert, 3] float64 and tets [n_tet, 4]
+    int32 (numpy arrays are copied to the device).  Returns (row_ptr int64,
+    cols int32, vals float64) CUDA tensors."""
+    torch = _torch()
+    dev = torch.device(device) if device is not None else (
+        xyz.device if isinstance(xyz, torch.Tensor) and xyz.is_cuda else torch.device("cuda"))
+    x = torch.as_tensor(xyz, dtype=torch.float64).to(dev).contiguous()
+    t = torch.as_tensor(tets, dtype=torch.int32).to(dev).contiguous()
+    if x.dim() != 2 or x.shape[1] != 3 or t.dim() != 2 or t.shape[1] != 4:
+        raise ValueError("xyz must be [n_vert, 3] and tets [n_tet, 4]")
+    L = _abi.lib()
+    nt = t.shape[0]
+    rp = torch.empty(nt + 1, dtype=torch.int64, device=dev)
+    nnz = C.c_int64()
+    with torch.cuda.device(dev):
+        st = _stream_ptr(dev)
+        _abi.check(L.spde_build_transfer_device_rows(int(n), x.shape[0], _ptr(x), nt, _ptr(t), _ptr(rp),
+                                                     C.byref(nnz), st))
+        ci = torch.empty(max(1, nnz.value), dtype=torch.int32, device=dev)
+        cv = torch.empty(max(1, nnz.value), dtype=torch.float64, device=dev)
+        _abi.check(L.spde_build_transfer_device_fill(int(n), x.shape[0], _ptr(x), nt, _ptr(t), _ptr(rp), _ptr(ci),
+                                                     _ptr(cv), st))
+    return rp, ci[:nnz.value], cv[:nnz.value]
+
+
 def coarsen_transfer_host(n_fine: int, row_ptr, cols, vals):
     """Pi of the (n_fine/2)^3 box onto the same tet mesh from Pi of the n_fine^3
     box (sum over each coarse cell's 8 children), by the library's host code.
@@ -122,11 +149,18 @@ def coarsen_transfer_host(n_fine: int, row_ptr, cols, vals):
     return row_ptr_c, cols_c, vals_c
 
 
-def transfer_row_order(row_ptr, cols):
-    """Row visiting order of the transfer SpMM (rows sorted by first cell)."""
+def transfer_row_order(row_ptr, cols, rows_first: bool = False):
+    """Row visiting order of the transfer SpMM (rows sorted by first cell).
+    rows_first: `cols` holds only each row's first column (one value per row,
+    read for the non-empty rows)."""
     rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
     ci = np.ascontiguousarray(cols, dtype=np.int32)
     order = np.empty(rp.size - 1, dtype=np.int32)
+    if rows_first:
+        # CSR with one entry per non-empty row: its first column
+        ne = rp[1:] > rp[:-1]
+        ci = np.ascontiguousarray(ci[:order.size][ne], dtype=np.int32)
+        rp = np.concatenate([[0], np.cumsum(ne)]).astype(np.int64)
     _abi.check(_abi.lib().spde_transfer_row_order(order.size, rp.ctypes.data, ci.ctypes.data, order.ctypes.data))
     return order
 
@@ -204,18 +238,31 @@ class Box:
         self._pi = None
 
     # -- transfer ---------------------------------------------------------
-    def set_mesh(self, xyz: np.ndarray, tets: np.ndarray):
-        """Build Pi for the tet mesh on the host and keep a device copy."""
+    def set_mesh(self, xyz: np.ndarray, tets: np.ndarray, builder: str = "host"):
+        """Build Pi for the tet mesh and keep it on the device: builder "host"
+        (the library's multithreaded host clipper, then a copy) or "device"
+        (the device clipper; the same matrix bit for bit)."""
+        if builder == "device":
+            rp, ci, cv = build_transfer_device(self.n, xyz, tets, device=self.device)
+            return self.set_transfer(rp, ci, cv)
+        if builder != "host":
+            raise ValueError("builder must be 'host' or 'device'")
         rp, ci, cv = build_transfer_host(self.n, xyz, tets)
         return self.set_transfer(rp, ci, cv)
 
     def set_transfer(self, row_ptr, cols, vals):
+        """Register Pi (CSR; numpy arrays are copied to the device, device
+        tensors are kept as they are)."""
         torch = _torch()
         d = self.device
-        rp = torch.as_tensor(np.asarray(row_ptr, dtype=np.int64)).to(d)
-        ci = torch.as_tensor(np.asarray(cols, dtype=np.int32)).to(d)
-        cv = torch.as_tensor(np.asarray(vals, dtype=np.float64)).to(d)
-        order = transfer_row_order(row_ptr, cols)
+        rp = torch.as_tensor(row_ptr, dtype=torch.int64).to(d)
+        ci = torch.as_tensor(cols, dtype=torch.int32).to(d)
+        cv = torch.as_tensor(vals, dtype=torch.float64).to(d)
+        # the SpMM row order is computed on the host from the row pointers and
+        # each row's first column
+        rp_h = rp.cpu().numpy()
+        first = ci[rp[:-1].clamp(max=max(ci.numel() - 1, 0))].cpu().numpy() if ci.numel() else np.zeros(0, np.int32)
+        order = transfer_row_order(rp_h, first, rows_first=True)
         od = torch.as_tensor(order).to(d)
         self._pi = (rp, ci, cv, od)
         self.n_tet = rp.numel() - 1

@@ -792,6 +792,50 @@ spde_status spde_transfer_coarsen(int n_fine, int64_t n_rows, const int64_t* row
   return SPDE_OK;
 }
 
+namespace {
+
+spde_status check_device_mesh(int n, int64_t n_vert, const double* xyz_dev, int64_t n_tet, const int32_t* tet_dev) {
+  if (n < 2 || n > 1024) return fail(SPDE_EINVAL, "n must lie in [2, 1024], got %d", n);
+  if (n_vert < 4 || n_vert > INT32_MAX || n_tet < 1 || n_tet > INT32_MAX)
+    return fail(SPDE_EINVAL, "mesh sizes out of range (n_vert %lld, n_tet %lld)", (long long)n_vert, (long long)n_tet);
+  if (!xyz_dev || !tet_dev) return fail(SPDE_EINVAL, "null mesh array");
+  return SPDE_OK;
+}
+
+}  // namespace
+
+spde_status spde_build_transfer_device_rows(int n, int64_t n_vert, const double* xyz_dev, int64_t n_tet,
+                                            const int32_t* tet_dev, int64_t* row_ptr_dev, int64_t* nnz,
+                                            void* stream) {
+  spde_status s = check_device_mesh(n, n_vert, xyz_dev, n_tet, tet_dev);
+  if (s != SPDE_OK) return s;
+  if (!row_ptr_dev || !nnz) return fail(SPDE_EINVAL, "null row_ptr or nnz");
+  const hipStream_t st = (hipStream_t)stream;
+  HIPCHK(launch_transfer_rows(n, xyz_dev, n_vert, tet_dev, n_tet, row_ptr_dev, st));
+  int64_t last = 0;
+  HIPCHK(hipMemcpyAsync(&last, row_ptr_dev + n_tet, sizeof last, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (last < 0) {
+    const int64_t b = -last - 1, t = b / 4;
+    const int code = (int)(b % 4);
+    const char* what = code == 1 ? "references a vertex out of range"
+                       : code == 2 ? "has a vertex outside [0,1]^3" : "is degenerate (zero volume)";
+    return fail(SPDE_EINVAL, "tet %lld %s", (long long)t, what);
+  }
+  *nnz = last;
+  return SPDE_OK;
+}
+
+spde_status spde_build_transfer_device_fill(int n, int64_t n_vert, const double* xyz_dev, int64_t n_tet,
+                                            const int32_t* tet_dev, const int64_t* row_ptr_dev, int32_t* col_dev,
+                                            double* val_dev, void* stream) {
+  spde_status s = check_device_mesh(n, n_vert, xyz_dev, n_tet, tet_dev);
+  if (s != SPDE_OK) return s;
+  if (!row_ptr_dev || !col_dev || !val_dev) return fail(SPDE_EINVAL, "null row_ptr, col or val");
+  HIPCHK(launch_transfer_fill(n, xyz_dev, n_vert, tet_dev, n_tet, row_ptr_dev, col_dev, val_dev, (hipStream_t)stream));
+  return SPDE_OK;
+}
+
 spde_status spde_set_transfer(spde_handle h, int64_t n_tet, int64_t nnz, const int64_t* row_ptr_dev,
                               const int32_t* col_dev, const double* val_dev) {
   Ctx* c = reinterpret_cast<Ctx*>(h);

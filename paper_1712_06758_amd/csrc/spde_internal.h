@@ -163,6 +163,12 @@ hipError_t launch_noise(int m, int coupled, uint64_t seed, uint64_t event0, int 
                         hipStream_t st);
 hipError_t launch_philox_raw(uint64_t seed, uint64_t event, uint64_t ctr0, uint64_t ctr1, int64_t nblocks,
                              uint64_t* out, hipStream_t st);
+// Device construction of the transfer: row lengths and pointers (rp[n_tet] < 0
+// flags the first invalid tet), then the entries.
+hipError_t launch_transfer_rows(int n, const double* xyz, int64_t n_vert, const int32_t* tets, int64_t n_tet,
+                                int64_t* rp, hipStream_t st);
+hipError_t launch_transfer_fill(int n, const double* xyz, int64_t n_vert, const int32_t* tets, int64_t n_tet,
+                                const int64_t* rp, int32_t* col, double* val, hipStream_t st);
 hipError_t launch_set_state(Scalars* sc, int slot0, int count, int state, hipStream_t st);
 hipError_t launch_mg_down(bool fp64, int shape, bool fine, const void* b0, const void* b1, void* rH,
                           const Level& L, int batch, const Scalars* sc, hipStream_t st);

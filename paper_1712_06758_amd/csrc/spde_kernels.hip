@@ -1583,4 +1583,5 @@ __global__ __launch_bounds__(kBlock) void k_convert(const TS* __restrict__ s, TD
 
 #include "spde_vcycle.inc"
 #include "spde_rng.inc"
+#include "spde_transfer.inc"
 #include "spde_launch.inc"

@@ -77,6 +77,28 @@ def test_noise_entry_points_validate_before_launching(lib):
     assert L.spde_last_error()
 
 
+def test_device_transfer_validates_before_launching(lib):
+    """Argument errors of the device transfer builder are caught on the host."""
+    buf = C.c_void_p(0x1000)           # never dereferenced: every call below fails validation first
+    nnz = C.c_int64()
+    rows = lib.spde_build_transfer_device_rows
+    assert rows(1, 8, buf, 6, buf, buf, C.byref(nnz), None) == -1          # n below 2
+    assert rows(2048, 8, buf, 6, buf, buf, C.byref(nnz), None) == -1       # n above 1024
+    assert rows(8, 3, buf, 6, buf, buf, C.byref(nnz), None) == -1          # fewer than 4 vertices
+    assert rows(8, 8, buf, 0, buf, buf, C.byref(nnz), None) == -1          # no tets
+    assert rows(8, 8, buf, 1 << 31, buf, buf, C.byref(nnz), None) == -1    # too many tets
+    assert rows(8, 8, None, 6, buf, buf, C.byref(nnz), None) == -1
+    assert rows(8, 8, buf, 6, None, buf, C.byref(nnz), None) == -1
+    assert rows(8, 8, buf, 6, buf, None, C.byref(nnz), None) == -1
+    assert rows(8, 8, buf, 6, buf, buf, None, None) == -1
+    fill = lib.spde_build_transfer_device_fill
+    assert fill(8, 8, buf, 6, buf, None, buf, buf, None) == -1
+    assert fill(8, 8, buf, 6, buf, buf, None, buf, None) == -1
+    assert fill(8, 8, buf, 6, buf, buf, buf, None, None) == -1
+    assert fill(0, 8, buf, 6, buf, buf, buf, buf, None) == -1
+    assert lib.spde_last_error()
+
+
 def test_set_coefficients_validation(lib):
     from paper_1712_06758_amd import _abi
     L = _abi.lib()
