@@ -260,9 +260,13 @@ class Box:
         cv = torch.as_tensor(vals, dtype=torch.float64).to(d)
         # the SpMM row order is computed on the host from the row pointers and
         # each row's first column
-        rp_h = rp.cpu().numpy()
-        first = ci[rp[:-1].clamp(max=max(ci.numel() - 1, 0))].cpu().numpy() if ci.numel() else np.zeros(0, np.int32)
-        order = transfer_row_order(rp_h, first, rows_first=True)
+        if isinstance(row_ptr, torch.Tensor) or isinstance(cols, torch.Tensor):
+            rp_h = rp.cpu().numpy()
+            first = (ci[rp[:-1].clamp(max=max(ci.numel() - 1, 0))].cpu().numpy() if ci.numel()
+                     else np.zeros(rp_h.size - 1, np.int32))
+            order = transfer_row_order(rp_h, first, rows_first=True)
+        else:
+            order = transfer_row_order(row_ptr, cols)
         od = torch.as_tensor(order).to(d)
         self._pi = (rp, ci, cv, od)
         self.n_tet = rp.numel() - 1
