@@ -121,3 +121,41 @@ def test_restoring_constants(torch_cuda):
     b = box.sample(xi, u_box=True)["u_box"]
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+
+_REF16 = {}
+
+
+def _ref16():
+    """Oracle fields for the 16^3 cell-wise case (one sparse factorisation)."""
+    if not _REF16:
+        n = 16
+        kc = smooth_field(n, 5.0, 40.0, 41)
+        gc = smooth_field(n, 1.0, 3.0, 42)
+        xi = xi_batch(n, [5, 6])
+        _REF16.update(kc=kc, gc=gc, xi=xi, u=V.solve_u_batch(n, kc, gc, xi))
+    return _REF16
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("shape,prec", [(13, "fp64"), (15, "mixed"), (10, "mixed")])
+def test_pipelined_up_kernel_each_face_kind_with_cell_coefficients(torch_cuda, kind, shape, prec):
+    """The finest-level up kernel is instantiated per face-block kind and per
+    cell-wise kappa; each combination, on pipelined tile shapes larger than the
+    16^3 box (partial blocks in z, and in x for the 32-wide tile), reaches the
+    oracle."""
+    say(f"pipelined up kernel: face kind {kind}, shape {shape}, {prec}, cell-wise kappa and g, n=16")
+    torch = torch_cuda
+    R = _ref16()
+    box = P().Box(16, 10.0, precision=prec, max_batch=2)
+    box.set_face_preconditioner(kind)
+    box.set_tiles(shape, shape)
+    box.set_coefficients(R["kc"], R["gc"])
+    assert box.get_tiles(0) == (shape, shape)
+    out = box.sample(torch.tensor(R["xi"], device="cuda"), u_box=True)
+    assert box.get_tiles(0) == (shape, shape)
+    u = out["u_box"].cpu().numpy()
+    errs = [rel_l2(u[b], R["u"][b]) for b in range(2)]
+    say(f"  iters {out['iters'].tolist()} errs {errs}")
+    assert max(errs) <= (1e-10 if prec == "fp64" else 1e-7)
