@@ -174,7 +174,8 @@ spde_status spde_set_transfer_order(spde_handle h, const int32_t* order_dev);
  *   u_box_dev  [batch][n^3]        box cell field  (nullable)
  *   sigma_dev  [batch][3n^2(n+1)]  flux sigma = -M^-1 B^T u (nullable)
  *   stream     hipStream_t to run on (NULL = default stream)
- *   iters_host [batch] MINRES iterations per sample (nullable)
+ *   iters_host [batch] MINRES iterations per sample, refinement passes
+ *              included (nullable)
  *   relres_host[batch] true relative residual ||F - A U|| / ||F|| with the
  *              flux recovered from u (nullable; computing it costs one extra
  *              pass, so NULL skips it unless sigma_dev is requested)
@@ -342,6 +343,20 @@ spde_status spde_set_split(spde_handle h, int ways);
  * traffic.  The multigrid V-cycle on the approximate Schur complement
  * kappa^2 W + B diag(M)^-1 B^T is the cell block in both cases. */
 spde_status spde_set_face_preconditioner(spde_handle h, int kind);
+
+/* Iterative refinement around the solve, in float64: after MINRES, the true
+ * residual r = F - A U is formed with the flux recovered from U (so only its
+ * cell row is nonzero); while ||r|| / ||F|| > target for a sample, and at most
+ * max_passes times, A d = r is solved by the same preconditioned MINRES and
+ * U += d for the samples above the target.  A pass stops at the relative
+ * tolerance 0.1 target / (largest residual above the target), kept within
+ * [rtol, 0.5].  This lets the mixed
+ * precision (float32 multigrid) reach residuals far below its rtol.
+ * target = 0 (default) turns refinement off; target in [0, 1), max_passes in
+ * [0, 16].  Applies to spde_sample and spde_sample_seeded (not to the
+ * continuous-batching slots).  relres_host then reports the final residual at
+ * no extra cost; a sample may stay above the target when max_passes runs out. */
+spde_status spde_set_refinement(spde_handle h, double target, int max_passes);
 
 /* Autotuning of the multigrid tile shapes (default on).  When on, the first
  * sample or V-cycle call of a handle times every admissible tile shape of each

@@ -410,6 +410,11 @@ class Box:
     def set_autotune(self, enable: bool):
         _abi.check(_abi.lib().spde_set_autotune(self._hh.h, int(bool(enable))))
 
+    def set_refinement(self, target: float, max_passes: int = 3):
+        """Float64 iterative refinement after each solve: correction solves on
+        the true residual until ||F - A U|| / ||F|| <= target (0 turns it off)."""
+        _abi.check(_abi.lib().spde_set_refinement(self._hh.h, float(target), int(max_passes)))
+
     def set_tiles(self, down: int, up: int, level: int = -1):
         """Fix the multigrid tile shapes (ids 0..17) of one level or all (-1)."""
         _abi.check(_abi.lib().spde_set_tiles(self._hh.h, int(level), int(down), int(up)))

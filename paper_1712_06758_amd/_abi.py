@@ -31,6 +31,7 @@ SIGNATURES = {
                                       C.POINTER(C.POINTER(C.c_int32)), C.POINTER(C.POINTER(C.c_double)),
                                       _i64p]),
     "spde_set_transfer": (C.c_int, [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp]),
+    "spde_set_refinement": (C.c_int, [_vp, C.c_double, C.c_int]),
     "spde_build_transfer_device_rows": (C.c_int, [C.c_int, C.c_int64, _vp, C.c_int64, _vp, _vp, _i64p, _vp]),
     "spde_build_transfer_device_fill": (C.c_int, [C.c_int, C.c_int64, _vp, C.c_int64, _vp, _vp, _vp, _vp, _vp]),
     "spde_transfer_coarsen": (C.c_int, [C.c_int, C.c_int64, _vp, _vp, _vp, C.POINTER(_i64p),

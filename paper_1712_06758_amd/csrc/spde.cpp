@@ -118,6 +118,8 @@ struct Ctx {
   std::map<int64_t, hipGraphExec_t> graphs;   // (first slot, half-iterations, batch) -> graph
   int split = 1;                 // 2: batches of 8+ run as two halves on two streams
   int expect_iters = 0;          // iterations (incl. the finishing pass) the last call needed
+  double refine_target = 0.0;     // > 0: refine until ||F - A U|| / ||F|| <= target (float64 residuals)
+  int refine_max = 0;             // at most this many refinement passes
   bool tuned = false;
   bool autotune = true;
   int face_precond = 1;          // 0 diag(M)^-1, 1 truncated Neumann series of M^-1
@@ -900,60 +902,135 @@ spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_de
     HIPCHK(hipEventRecord(c->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0));
   }
+  // MINRES iterations in blocks of the poll interval until no sample is active.
+  // expect: iterations the previous call needed (0: unknown); the block that
+  // would pass it stops there, so that a batch like the last one is not
+  // carried through idle iterations.
+  auto iterate = [&](int expect, int& launched) -> spde_status {
+    launched = 0;
+    const int cap = c->max_iter + 2;
+    bool all_done = false;
+    while (!all_done && launched < cap + c->poll) {
+      int count = c->poll;
+      if (expect > launched) count = std::min(count, expect - launched);
+      spde_status s2 = enqueue_block(c, V0, b1, st, graphs, launched, count);
+      if (s2 != SPDE_OK) return s2;
+      if (split) {
+        s2 = enqueue_block(c, V1, batch - b1, c->aux_stream, graphs, launched, count);
+        if (s2 != SPDE_OK) return s2;
+        HIPCHK(hipEventRecord(c->ev_join, c->aux_stream));
+        HIPCHK(hipStreamWaitEvent(st, c->ev_join, 0));
+      }
+      launched += count;
+      HIPCHK(hipMemcpyAsync(c->host_sc, c->F.sc, batch * sizeof(Scalars), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      all_done = true;
+      for (int b = 0; b < batch; ++b) {
+        if (c->host_sc[b].state == ST_ACTIVE) { all_done = false; break; }
+      }
+    }
+    return SPDE_OK;
+  };
   int launched = 0;
-  const int cap = c->max_iter + 2;
-  bool all_done = false;
-  while (!all_done && launched < cap + c->poll) {
-    // Blocks of poll-interval iterations; the block that would pass the
-    // iteration count at which the previous call finished stops there, so that
-    // a batch like the last one is not carried through idle iterations.
-    int count = c->poll;
-    if (c->expect_iters > launched) count = std::min(count, c->expect_iters - launched);
-    s = enqueue_block(c, V0, b1, st, graphs, launched, count);
-    if (s != SPDE_OK) return s;
-    if (split) {
-      s = enqueue_block(c, V1, batch - b1, c->aux_stream, graphs, launched, count);
-      if (s != SPDE_OK) return s;
-      HIPCHK(hipEventRecord(c->ev_join, c->aux_stream));
-      HIPCHK(hipStreamWaitEvent(st, c->ev_join, 0));
-    }
-    launched += count;
-    HIPCHK(hipMemcpyAsync(c->host_sc, c->F.sc, batch * sizeof(Scalars), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    all_done = true;
-    for (int b = 0; b < batch; ++b) {
-      const int stt = c->host_sc[b].state;
-      if (stt == ST_ACTIVE) { all_done = false; break; }
-    }
-  }
+  s = iterate(c->expect_iters, launched);
+  if (s != SPDE_OK) return s;
   bool notconv = false, failed = false;
   int most = 0;
+  std::vector<int> total(batch, 0);
   for (int b = 0; b < batch; ++b) {
     const Scalars& sc = c->host_sc[b];
     if (sc.state == ST_FAILED) failed = true;
     if (sc.state == ST_ACTIVE || (sc.flags & FL_NOTCONV)) notconv = true;
-    if (iters_host) iters_host[b] = sc.state == ST_ACTIVE ? launched : sc.iters;
+    total[b] = sc.state == ST_ACTIVE ? launched : sc.iters;
     if (sc.state == ST_FINISH || sc.state == ST_DONE) most = std::max(most, sc.iters);
   }
   // a converged sample needs its iterations plus the finishing pass
   c->expect_iters = (!notconv && !failed && most > 0) ? most + 1 : 0;
   HIPCHK(launch_fix_solution(c->F, bx, batch, 0, st));
+  // the load F_u: the caller's noise, or the generated noise drawn again into
+  // a Lanczos buffer that a finished solve no longer needs
+  const double* xi_res = src.xi;
+  auto load_for_residual = [&]() -> spde_status {
+    if (!src.xi) {
+      HIPCHK(launch_noise(bx.n, src.coupled, src.seed, src.event0, batch, c->F.vu[0], st));
+      xi_res = c->F.vu[0];
+    }
+    return SPDE_OK;
+  };
+  // Iterative refinement in float64: with r = F - A U (flux recovered from U,
+  // so only the cell row is nonzero), solve A d = r by the same MINRES and set
+  // U += d, for the samples whose relative true residual exceeds the target.
+  bool res_final = false;   // host_res holds the residual of the current U
+  if (c->refine_target > 0.0 && !failed) {
+    for (int pass = 0;; ++pass) {
+      s = load_for_residual();
+      if (s != SPDE_OK) return s;
+      {
+        Timed t(c, KID_FLUX, 0, st);
+        HIPCHK(launch_flux(c->F.x, c->F.vs[0], nullptr, bx, batch, st));
+      }
+      {
+        Timed t(c, KID_RESID, 0, st);
+        HIPCHK(launch_resid(c->F.vs[0], c->F.x, xi_res, scale, bx, batch, c->F.part_pb, c->resid_out, c->F.vu[1],
+                            st));
+      }
+      HIPCHK(hipMemcpyAsync(c->host_res, c->resid_out, batch * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      res_final = true;
+      bool need_any = false;
+      double worst = 0.0;
+      for (int b = 0; b < batch; ++b) {
+        if (!(c->host_res[b] <= c->refine_target)) {
+          need_any = true;
+          worst = std::max(worst, c->host_res[b]);
+        }
+      }
+      if (!need_any || pass >= c->refine_max) break;
+      // the pass has to reduce its residual by target / worst only (a factor
+      // of 10 to spare); never tighter than the configured rtol, which the
+      // preconditioned MINRES is known to reach
+      const double tol_pass = std::isfinite(worst) && worst > 0.0
+                                  ? std::min(0.5, std::max(c->rtol, 0.1 * c->refine_target / worst))
+                                  : c->rtol;
+      HIPCHK(launch_init_correction(c->F, bx, batch, tol_pass, c->max_iter, st));
+      for (int b = 0; b < batch; ++b)
+        if (c->host_res[b] <= c->refine_target) HIPCHK(launch_set_state(c->F.sc, b, 1, ST_DONE, st));
+      if (split) {   // the second stream's half starts after the pass's set-up
+        HIPCHK(hipEventRecord(c->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0));
+      }
+      int lp = 0;
+      s = iterate(0, lp);
+      if (s != SPDE_OK) return s;
+      for (int b = 0; b < batch; ++b) {
+        const Scalars& sc = c->host_sc[b];
+        if (c->host_res[b] <= c->refine_target) continue;   // not refined in this pass
+        if (sc.state == ST_FAILED) failed = true;
+        if (sc.state == ST_ACTIVE || (sc.flags & FL_NOTCONV)) notconv = true;
+        total[b] += sc.state == ST_ACTIVE ? lp : sc.iters;
+      }
+      HIPCHK(launch_fix_solution(c->F, bx, batch, 0, st));
+      res_final = false;
+      if (failed) break;
+    }
+  }
+  if (iters_host)
+    for (int b = 0; b < batch; ++b) iters_host[b] = total[b];
   if (u_box_dev) HIPCHK(hipMemcpyAsync(u_box_dev, c->F.x, (size_t)batch * bx.nc * 8, hipMemcpyDeviceToDevice, st));
-  if (sigma_dev || relres_host) {
-    double* sig_int = relres_host ? c->F.vs[0] : nullptr;
+  // (after refinement host_res already holds the residual of the final U)
+  const bool need_res = relres_host && !res_final;
+  if (sigma_dev || need_res) {
+    double* sig_int = need_res ? c->F.vs[0] : nullptr;
     {
       Timed t(c, KID_FLUX, 0, st);
       HIPCHK(launch_flux(c->F.x, sig_int, sigma_dev, bx, batch, st));
     }
-    if (relres_host) {
-      const double* xi = src.xi;
-      if (!xi) {   // draw the noise again into a Lanczos buffer the finished solve no longer needs
-        HIPCHK(launch_noise(bx.n, src.coupled, src.seed, src.event0, batch, c->F.vu[0], st));
-        xi = c->F.vu[0];
-      }
+    if (need_res) {
+      s = load_for_residual();
+      if (s != SPDE_OK) return s;
       {
         Timed t(c, KID_RESID, 0, st);
-        HIPCHK(launch_resid(sig_int, c->F.x, xi, scale, bx, batch, c->F.part_pb, c->resid_out, st));
+        HIPCHK(launch_resid(sig_int, c->F.x, xi_res, scale, bx, batch, c->F.part_pb, c->resid_out, nullptr, st));
       }
       HIPCHK(hipMemcpyAsync(c->host_res, c->resid_out, batch * sizeof(double), hipMemcpyDeviceToHost, st));
     }
@@ -1232,6 +1309,16 @@ spde_status spde_set_graphs(spde_handle h, int enable) {
   Ctx* c = reinterpret_cast<Ctx*>(h);
   if (!c) return fail(SPDE_EINVAL, "null handle");
   c->use_graphs = enable != 0;
+  return SPDE_OK;
+}
+
+spde_status spde_set_refinement(spde_handle h, double target, int max_passes) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (!(target >= 0.0 && target < 1.0)) return fail(SPDE_EINVAL, "refinement target must lie in [0, 1)");
+  if (max_passes < 0 || max_passes > 16) return fail(SPDE_EINVAL, "refinement passes must lie in [0, 16]");
+  c->refine_target = target;
+  c->refine_max = target > 0.0 ? max_passes : 0;
   return SPDE_OK;
 }
 

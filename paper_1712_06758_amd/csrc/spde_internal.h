@@ -27,7 +27,9 @@ enum SlotState : int {
 
 enum SlotFlags : int {
   FL_ZERO    = 1,  // right-hand side was exactly zero: solution is 0
-  FL_NOTCONV = 2   // stopped at max_iter
+  FL_NOTCONV = 2,  // stopped at max_iter
+  FL_ACCUM   = 4   // refinement pass: the solve adds its solution to x (which holds the
+                   // previous iterate) instead of overwriting it
 };
 
 // MINRES scalars of one sample.  Notation: iteration j works on the Lanczos
@@ -184,7 +186,10 @@ hipError_t launch_fix_solution(const Fields& F, const Box& bx, int batch, int sl
 hipError_t launch_flux(const double* u, double* sig_int, double* sig_ext, const Box& bx, int batch,
                        hipStream_t st);
 hipError_t launch_resid(const double* sig, const double* u, const double* xi, double scale, const Box& bx,
-                        int batch, double* part, double* out, hipStream_t st);
+                        int batch, double* part, double* out, double* rhs, hipStream_t st);
+// Refinement pass: v_1 = [0; the load already in vu[1]], scalars reset with FL_ACCUM.
+hipError_t launch_init_correction(const Fields& F, const Box& bx, int batch, double tol, int max_iter,
+                                  hipStream_t st);
 hipError_t launch_spmm(const int64_t* rp, const int32_t* ci, const double* cv, const double* u, double* out,
                        int64_t ntet, int64_t nnz, int64_t nc, int batch, const int32_t* order, hipStream_t st);
 hipError_t launch_restrict_noise(const double* xf, double* xc, int nf, int batch, hipStream_t st);

@@ -198,6 +198,24 @@ __global__ __launch_bounds__(kBlock) void k_init(Fields F, Box bx, const double*
   if (blk == 0 && threadIdx.x == 0) init_scalars(F, slot, tol, max_iter);
 }
 
+// Refinement pass (iterative refinement in float64 around the whole solve):
+// v_1 = [0; r] with r = F - A U already in vu[1], MINRES state reset, and
+// FL_ACCUM so that the pass adds its correction to x = U.
+__global__ __launch_bounds__(kBlock) void k_init_correction(Fields F, Box bx, int nb, double tol, int max_iter) {
+  const int slot = blockIdx.x / nb;
+  const int blk = blockIdx.x - slot * nb;
+  const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
+  if (c < bx.nc) {
+    F.vs[1][face_off(slot, 0, bx.nc) + c] = 0.0;
+    F.vs[1][face_off(slot, 1, bx.nc) + c] = 0.0;
+    F.vs[1][face_off(slot, 2, bx.nc) + c] = 0.0;
+  }
+  if (blk == 0 && threadIdx.x == 0) {
+    init_scalars(F, slot, tol, max_iter);
+    F.sc[slot].flags = FL_ACCUM;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // multigrid: smooth from zero + residual + restriction (one level, 3-D tile)
 //
@@ -1112,6 +1130,7 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
   // scalars before any store (after a store they could no longer be scalar loads)
   const double zs = S->zs, av = S->a_v, bv = S->b_v;
   const double sww = S->ww, swwp = S->ww_prev, sxw = S->xw, sxp = S->xpend;
+  const bool acc = S->flags & FL_ACCUM;   // refinement pass: x holds the previous iterate
 
   // Direction and solution updates (unnormalised directions, see Scalars):
   //   W_{j+1} = zs zhat_j + ww W_j + ww_prev W_{j-1}      (W_j in w[pq], W_{j-1} in w[p])
@@ -1121,7 +1140,7 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
   auto x_update = [&](double wj, double wjm1) {
     if (upd_x) {
       const double inc = sxp * wjm1 + sxw * wj;
-      F.x[co + c] = j == 2 ? inc : F.x[co + c] + inc;
+      F.x[co + c] = (j == 2 && !acc) ? inc : F.x[co + c] + inc;
     }
   };
   if (!active) {   // the finishing pass only applies the last solution update
@@ -1208,10 +1227,11 @@ __global__ __launch_bounds__(kBlock) void k_operator_col(Fields F, Box bx, int n
   const bool upd_x = wm >= 1 && ((j & 1) == 0 || state == ST_FINISH);
   const double zs = S->zs, av = S->a_v, bv = S->b_v;
   const double sww = S->ww, swwp = S->ww_prev, sxw = S->xw, sxp = S->xpend;
+  const bool acc = S->flags & FL_ACCUM;   // refinement pass: x holds the previous iterate
   auto x_update = [&](int64_t c, double wj, double wjm1) {
     if (upd_x) {
       const double inc = sxp * wjm1 + sxw * wj;
-      F.x[co + c] = j == 2 ? inc : F.x[co + c] + inc;
+      F.x[co + c] = (j == 2 && !acc) ? inc : F.x[co + c] + inc;
     }
   };
   if (!active) {
@@ -1331,13 +1351,14 @@ __global__ void k_set_state(Scalars* sc, int slot0, int count, int state) {
   if (i < count) sc[slot0 + i].state = state;
 }
 
-// Zero / NaN the solution of slots that finished with FL_ZERO / ST_FAILED.
+// Zero / NaN the solution of slots that finished with FL_ZERO / ST_FAILED (a
+// refinement pass with a zero load leaves the previous iterate in place).
 __global__ __launch_bounds__(kBlock) void k_fix_solution(Fields F, Box bx, int nb, int slot0) {
   const int rel = blockIdx.x / nb, blk = blockIdx.x - rel * nb;
   const int slot = slot0 + rel;
   const Scalars* S = F.sc + slot;
-  const bool zero = S->flags & FL_ZERO;
   const bool fail = S->state == ST_FAILED;
+  const bool zero = (S->flags & FL_ZERO) && !(S->flags & FL_ACCUM);
   if (!zero && !fail) return;
   const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
   if (c < bx.nc) F.x[cell_off(slot, bx.nc) + c] = zero ? 0.0 : __builtin_nan("");
@@ -1412,10 +1433,12 @@ __global__ __launch_bounds__(kBlock) void k_flux(const double* __restrict__ u, d
 
 // True residual of the cell row with the recovered flux:
 //   r = F_u - (B sigma - kappa^2 h^3 u),  F_u = -g h^{3/2} xi.
-// Per-block partial sums of |r|^2 and |F_u|^2.
+// Per-block partial sums of |r|^2 and |F_u|^2; r itself into rhs (if not null),
+// the load of a refinement pass.  (The face row of the residual vanishes up
+// to rounding: sigma = -M^-1 B^T u solves it.)
 __global__ __launch_bounds__(kBlock) void k_resid(const double* __restrict__ sig, const double* __restrict__ u,
                                                   const double* __restrict__ xi, double scale, Box bx,
-                                                  int nb, double* __restrict__ part) {
+                                                  int nb, double* __restrict__ part, double* __restrict__ rhs) {
   __shared__ double red[kBlock / 64];
   const int slot = blockIdx.x / nb, blk = blockIdx.x - slot * nb;
   const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
@@ -1433,6 +1456,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(const double* __restrict__ sig
     const double sc_c = bx.gfld ? -bx.gfld[c] * bx.h15 : scale;
     const double fu = sc_c * xi[cell_off(slot, nc) + c];
     const double r = fu - (bx.h2 * div - cell_k2h3(bx, c) * uc);
+    if (rhs) rhs[cell_off(slot, nc) + c] = r;
     rr = r * r;
     ff = fu * fu;
   }

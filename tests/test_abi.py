@@ -99,6 +99,19 @@ def test_device_transfer_validates_before_launching(lib):
     assert lib.spde_last_error()
 
 
+def test_set_refinement_validation(lib):
+    from paper_1712_06758_amd import _abi
+    L = _abi.lib()
+    assert L.spde_set_refinement(None, 1e-12, 2) == -1
+    st, h = setup(lib, 16)
+    assert st == 0
+    for target, passes in [(-1e-3, 2), (1.0, 2), (float("nan"), 2), (1e-12, -1), (1e-12, 17)]:
+        assert L.spde_set_refinement(h, target, passes) == -1, (target, passes)
+    assert L.spde_set_refinement(h, 1e-12, 3) == 0
+    assert L.spde_set_refinement(h, 0.0, 0) == 0
+    lib.spde_destroy(h)
+
+
 def test_set_coefficients_validation(lib):
     from paper_1712_06758_amd import _abi
     L = _abi.lib()
