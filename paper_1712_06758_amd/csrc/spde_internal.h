@@ -172,6 +172,8 @@ hipError_t launch_transfer_rows(int n, const double* xyz, int64_t n_vert, const 
 hipError_t launch_transfer_fill(int n, const double* xyz, int64_t n_vert, const int32_t* tets, int64_t n_tet,
                                 const int64_t* rp, int32_t* col, double* val, hipStream_t st);
 hipError_t launch_set_state(Scalars* sc, int slot0, int count, int state, hipStream_t st);
+// Per-sample scalars of a steady-state operator pass (autotuner timing).
+hipError_t launch_tune_scalars(Scalars* sc, int batch, hipStream_t st);
 hipError_t launch_mg_down(bool fp64, int shape, bool fine, const void* b0, const void* b1, void* rH,
                           const Level& L, int batch, const Scalars* sc, hipStream_t st);
 hipError_t launch_mg_up(bool fp64, int shape, bool fine, const void* b0, const void* b1, const void* eH, void* o0,
