@@ -102,7 +102,7 @@ def cpu_baseline(n, kappa, g, xi_np):
         oracle.sample_box(n, kappa, g, xi_np[b])
     t_spec = time.perf_counter() - t0
     return {"value": round(1.0 / t_minres, 5), "unit": "samples/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 of the 64 noise vectors of the {n}^3 workload through the oracle's preconditioned "
+            "sample": f"1 of the {xi_np.shape[0]} noise vectors of the {n}^3 workload through the oracle's preconditioned "
                       f"MINRES (SciPy sparse operator, exact DCT Schur preconditioner, rtol 3e-11, {it} "
                       f"iterations): {t_minres:.1f} s; transfer apply not included",
             "spectral_exact_samples_per_s": round(xi_np.shape[0] / t_spec, 3),
@@ -136,8 +136,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["box64", "box128", "box256"], default="box128",
-                    help="named workload (the 64^3 x 32 and 256^3 x 8 configurations beside the default)")
+    ap.add_argument("--workload", choices=["box16", "box64", "box128", "box256"], default="box128",
+                    help="named workload (the 16^3 x 1, 64^3 x 32 and 256^3 x 8 configurations beside the default)")
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
