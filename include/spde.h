@@ -189,6 +189,20 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev,
                         double* u_tet_dev, double* u_box_dev, double* sigma_dev,
                         void* stream, int* iters_host, double* relres_host);
 
+/* Warm-started coupled fine solve (the MLMC coupling of levels l and l+1):
+ * as spde_sample, but MINRES starts from U0 = P u_c, the coarse solution
+ * u_coarse_dev [batch][(n/2)^3] (float64, cell order of the (n/2)^3 box)
+ * injected into its 8 children.  The true residual r0 = F - A U0 (flux
+ * recovered from U0) is solved for by one correction solve that adds to U0,
+ * stopped at the relative tolerance rtol ||F|| / max ||r0|| (within
+ * [rtol, 0.5]), so the result has the accuracy of a cold solve.  iters_host
+ * counts the correction solve's iterations.  White noise puts most of the load
+ * at the grid scale, which the coarse field cannot represent, so the start
+ * saves few iterations (measured: under one at these sizes). */
+spde_status spde_sample_warm(spde_handle h, int batch, const double* xi_dev, const double* u_coarse_dev,
+                             double* u_tet_dev, double* u_box_dev, double* sigma_dev, void* stream,
+                             int* iters_host, double* relres_host);
+
 /* Noise of the coupled coarse sample (eq. ml-linsys, F_{l+1} = P^T F_l):
  * xi_c[I] = 8^{-1/2} * sum of xi_f over the 8 children of coarse cell I.
  *   xi_f_dev [batch][n_fine^3] -> xi_c_dev [batch][(n_fine/2)^3]

@@ -320,6 +320,16 @@ class Box:
         return self._run(B, lambda *a: _abi.lib().spde_sample(self._hh.h, B, _ptr(xi), *a),
                          u_tet, u_box, sigma, relres, allow_notconv)
 
+    def sample_warm(self, xi, u_coarse, u_tet=True, u_box=False, sigma=False, relres=False,
+                    allow_notconv=False):
+        """As sample(), with MINRES warm-started from the coupled coarse solution
+        u_coarse [B, (n/2)^3] (float64, on the device) injected into the box."""
+        B = xi.shape[0]
+        _check_dev_f64(xi, (B, self.n ** 3), "xi")
+        _check_dev_f64(u_coarse, (B, (self.n // 2) ** 3), "u_coarse")
+        return self._run(B, lambda *a: _abi.lib().spde_sample_warm(self._hh.h, B, _ptr(xi), _ptr(u_coarse), *a),
+                         u_tet, u_box, sigma, relres, allow_notconv)
+
     def sample_seeded(self, seed: int, event0: int = 0, batch: int = 1, coupled: bool = False, u_tet=True,
                       u_box=False, sigma=False, relres=False, allow_notconv=False):
         """Fields for the events event0 .. event0 + batch - 1 of `seed`, with the

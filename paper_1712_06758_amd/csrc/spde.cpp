@@ -879,7 +879,8 @@ spde_status check_noise_grid(const Ctx* c, int coupled) {
 }
 
 spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_dev, double* u_box_dev,
-                        double* sigma_dev, void* stream, int* iters_host, double* relres_host) {
+                        double* sigma_dev, void* stream, int* iters_host, double* relres_host,
+                        const double* warm_uc = nullptr) {
   spde_status s = check_ready(c);
   if (s != SPDE_OK) return s;
   if (batch < 1) return fail(SPDE_EINVAL, "batch must be >= 1");
@@ -891,12 +892,54 @@ spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_de
   const double scale = -c->g * std::pow(bx.h, 1.5);
   s = autotune(c, st);
   if (s != SPDE_OK) return s;
-  {
+  // the load F_u: the caller's noise, or the generated noise drawn again into
+  // a Lanczos buffer that no running solve uses
+  const double* xi_res = src.xi;
+  auto load_for_residual = [&]() -> spde_status {
+    if (!src.xi) {
+      HIPCHK(launch_noise(bx.n, src.coupled, src.seed, src.event0, batch, c->F.vu[0], st));
+      xi_res = c->F.vu[0];
+    }
+    return SPDE_OK;
+  };
+  // True residual r = F - A U of the current U = x, with the flux recovered
+  // from U (so only the cell row is nonzero): ||r|| / ||F|| into host_res, and
+  // r into vu[1], the load of a correction solve.
+  auto residual = [&]() -> spde_status {
+    spde_status s2 = load_for_residual();
+    if (s2 != SPDE_OK) return s2;
+    {
+      Timed t(c, KID_FLUX, 0, st);
+      HIPCHK(launch_flux(c->F.x, c->F.vs[0], nullptr, bx, batch, st));
+    }
+    {
+      Timed t(c, KID_RESID, 0, st);
+      HIPCHK(launch_resid(c->F.vs[0], c->F.x, xi_res, scale, bx, batch, c->F.part_pb, c->resid_out, c->F.vu[1],
+                          st));
+    }
+    HIPCHK(hipMemcpyAsync(c->host_res, c->resid_out, batch * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return SPDE_OK;
+  };
+  if (!warm_uc) {
     Timed t(c, KID_INIT, 0, st);
     if (src.xi) HIPCHK(launch_init(c->F, bx, src.xi, scale, batch, c->rtol, c->max_iter, 0, st));
     else
       HIPCHK(launch_init_gen(c->F, bx, src.seed, src.event0, src.coupled, scale, batch, c->rtol, c->max_iter, 0,
                              st));
+  } else {
+    // Warm start from the coupled coarse solution: U0 = P u_c, then one
+    // correction solve on r0 = F - A U0 that adds to x, stopped where the cold
+    // solve would stop relative to F: its tolerance is rtol ||F|| / ||r0||.
+    HIPCHK(launch_inject_coarse(warm_uc, c->F.x, bx.n, batch, st));
+    s = residual();
+    if (s != SPDE_OK) return s;
+    double worst = 0.0;
+    for (int b = 0; b < batch; ++b)
+      if (std::isfinite(c->host_res[b])) worst = std::max(worst, c->host_res[b]);
+    const double tol = worst > 0.0 ? std::min(0.5, std::max(c->rtol, c->rtol / worst)) : c->rtol;
+    Timed t(c, KID_INIT, 0, st);
+    HIPCHK(launch_init_correction(c->F, bx, batch, tol, c->max_iter, st));
   }
   const bool graphs = c->use_graphs && c->timing != 1 && st != nullptr;
   // A batch of 8 or more runs as two halves on two streams, so that the
@@ -955,35 +998,14 @@ spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_de
   // a converged sample needs its iterations plus the finishing pass
   c->expect_iters = (!notconv && !failed && most > 0) ? most + 1 : 0;
   HIPCHK(launch_fix_solution(c->F, bx, batch, 0, st));
-  // the load F_u: the caller's noise, or the generated noise drawn again into
-  // a Lanczos buffer that a finished solve no longer needs
-  const double* xi_res = src.xi;
-  auto load_for_residual = [&]() -> spde_status {
-    if (!src.xi) {
-      HIPCHK(launch_noise(bx.n, src.coupled, src.seed, src.event0, batch, c->F.vu[0], st));
-      xi_res = c->F.vu[0];
-    }
-    return SPDE_OK;
-  };
   // Iterative refinement in float64: with r = F - A U (flux recovered from U,
   // so only the cell row is nonzero), solve A d = r by the same MINRES and set
   // U += d, for the samples whose relative true residual exceeds the target.
   bool res_final = false;   // host_res holds the residual of the current U
   if (c->refine_target > 0.0 && !failed) {
     for (int pass = 0;; ++pass) {
-      s = load_for_residual();
+      s = residual();
       if (s != SPDE_OK) return s;
-      {
-        Timed t(c, KID_FLUX, 0, st);
-        HIPCHK(launch_flux(c->F.x, c->F.vs[0], nullptr, bx, batch, st));
-      }
-      {
-        Timed t(c, KID_RESID, 0, st);
-        HIPCHK(launch_resid(c->F.vs[0], c->F.x, xi_res, scale, bx, batch, c->F.part_pb, c->resid_out, c->F.vu[1],
-                            st));
-      }
-      HIPCHK(hipMemcpyAsync(c->host_res, c->resid_out, batch * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
       res_final = true;
       bool need_any = false;
       double worst = 0.0;
@@ -1067,6 +1089,17 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* 
   NoiseSrc src;
   src.xi = xi_dev;
   return sample_impl(c, batch, src, u_tet_dev, u_box_dev, sigma_dev, stream, iters_host, relres_host);
+}
+
+spde_status spde_sample_warm(spde_handle h, int batch, const double* xi_dev, const double* u_coarse_dev,
+                             double* u_tet_dev, double* u_box_dev, double* sigma_dev, void* stream, int* iters_host,
+                             double* relres_host) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (!xi_dev || !u_coarse_dev) return fail(SPDE_EINVAL, "xi or u_coarse is null");
+  NoiseSrc src;
+  src.xi = xi_dev;
+  return sample_impl(c, batch, src, u_tet_dev, u_box_dev, sigma_dev, stream, iters_host, relres_host, u_coarse_dev);
 }
 
 spde_status spde_sample_seeded(spde_handle h, int batch, uint64_t seed, uint64_t event0, int coupled,

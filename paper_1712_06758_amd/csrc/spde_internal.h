@@ -189,6 +189,8 @@ hipError_t launch_flux(const double* u, double* sig_int, double* sig_ext, const 
                        hipStream_t st);
 hipError_t launch_resid(const double* sig, const double* u, const double* xi, double scale, const Box& bx,
                         int batch, double* part, double* out, double* rhs, hipStream_t st);
+// Warm start: x[slot] = the (n/2)^3 field uc[slot] injected into its children.
+hipError_t launch_inject_coarse(const double* uc, double* x, int n, int batch, hipStream_t st);
 // Refinement pass: v_1 = [0; the load already in vu[1]], scalars reset with FL_ACCUM.
 hipError_t launch_init_correction(const Fields& F, const Box& bx, int batch, double tol, int max_iter,
                                   hipStream_t st);

@@ -1525,6 +1525,23 @@ __global__ __launch_bounds__(kBlock) void k_spmm(const int64_t* __restrict__ rp,
 }
 
 // ---------------------------------------------------------------------------
+// warm start of a coupled fine solve: x = P u_c, the coarse cell field of the
+// (n/2)^3 box injected into its 8 children (P0 prolongation, the nested
+// piecewise-constant interpolation of the box hierarchy)
+
+__global__ __launch_bounds__(kBlock) void k_inject_coarse(const double* __restrict__ uc, double* __restrict__ x,
+                                                          int n, int batch) {
+  const int64_t nc = (int64_t)n * n * n;
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= nc * batch) return;
+  const int slot = (int)(gid / nc);
+  const int64_t c = gid - (int64_t)slot * nc;
+  const int m = n >> 1;
+  const int i = (int)(c % n), j = (int)((c / n) % n), k = (int)(c / ((int64_t)n * n));
+  x[gid] = uc[(int64_t)slot * m * m * m + (i >> 1) + (int64_t)m * ((j >> 1) + (int64_t)m * (k >> 1))];
+}
+
+// ---------------------------------------------------------------------------
 // noise restriction (eq. ml-linsys): xi_c[I] = 8^{-1/2} sum of the 8 children
 
 __global__ __launch_bounds__(kBlock) void k_restrict_noise(const double* __restrict__ xf, double* __restrict__ xc,
