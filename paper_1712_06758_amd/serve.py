@@ -436,11 +436,19 @@ def main(argv=None):
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--levels", default="32,64,128,256")
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--slots", default="",
+                    help="slots per box size overriding the defaults, e.g. 32:512,64:128,256:8")
     args = ap.parse_args(argv)
     from workloads import SERVE_LEVELS, SERVE_CORR_LEN, poisson_arrivals
     levels = [int(x) for x in args.levels.split(",")]
     rates = {n: SERVE_LEVELS[n] * args.scale for n in levels}
-    srv = build_gpu_server(levels, SERVE_CORR_LEN, args.precision)
+    slots = None
+    if args.slots:
+        over = {int(k): int(v) for k, v in (item.split(":") for item in args.slots.split(","))}
+        sizes = sorted(set(levels) | {n // 2 for n in levels if n != min(levels)})
+        base = {16: 128, 32: 128, 64: 64, 128: 16, 256: 4}
+        slots = {n: over.get(n, base.get(n, 8)) for n in sizes}
+    srv = build_gpu_server(levels, SERVE_CORR_LEN, args.precision, slots=slots)
     # warm-up: one request per level, not timed
     warm = [(0.0, n, 10 ** 6 + i) for i, n in enumerate(levels)]
     srv.run(warm)
