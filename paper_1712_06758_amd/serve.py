@@ -386,6 +386,13 @@ class Server:
 # GPU server construction and the command-line load run
 
 
+# Slots per box size.  Small levels get many: a request then never waits for a
+# free slot, and its latency is set by how fast its engine steps while sharing
+# the GPU.  (More slots on the small levels raise the sustainable request rate
+# at the cost of latency.)
+DEFAULT_SLOTS = {16: 128, 32: 128, 64: 64, 128: 16, 256: 4}
+
+
 def build_gpu_server(levels=(32, 64, 128, 256), corr_len=0.05, precision="mixed", slots=None,
                      hbm_budget=None, device=None, keep_results=False, poll=4, noise_seed=2024):
     """Engines for the levels and their coupled coarse boxes.  A request's noise
@@ -399,10 +406,7 @@ def build_gpu_server(levels=(32, 64, 128, 256), corr_len=0.05, precision="mixed"
     g = g_unit_variance(kappa)
     levels = sorted(levels)
     sizes = sorted(set(levels) | {n // 2 for n in levels if n != levels[0]})
-    # small levels get many slots: a request then never waits for a free slot,
-    # and its latency is set by how fast its engine steps while sharing the GPU
-    default_slots = {16: 128, 32: 128, 64: 64, 128: 16, 256: 4}
-    slots = slots or {n: default_slots.get(n, 8) for n in sizes}
+    slots = slots or {n: DEFAULT_SLOTS.get(n, 8) for n in sizes}
     engines = {}
     meshes = {n: serve_mesh(n) for n in levels}
     # finest first: the coarse part of level n projects with Pi of the (n/2)^3 box
@@ -446,8 +450,7 @@ def main(argv=None):
     if args.slots:
         over = {int(k): int(v) for k, v in (item.split(":") for item in args.slots.split(","))}
         sizes = sorted(set(levels) | {n // 2 for n in levels if n != min(levels)})
-        base = {16: 128, 32: 128, 64: 64, 128: 16, 256: 4}
-        slots = {n: over.get(n, base.get(n, 8)) for n in sizes}
+        slots = {n: over.get(n, DEFAULT_SLOTS.get(n, 8)) for n in sizes}
     srv = build_gpu_server(levels, SERVE_CORR_LEN, args.precision, slots=slots)
     # warm-up: one request per level, not timed
     warm = [(0.0, n, 10 ** 6 + i) for i, n in enumerate(levels)]
