@@ -372,6 +372,19 @@ spde_status spde_set_face_preconditioner(spde_handle h, int kind);
  * no extra cost; a sample may stay above the target when max_passes runs out. */
 spde_status spde_set_refinement(spde_handle h, double target, int max_passes);
 
+/* A HIP stream whose kernels run only on the compute units whose bits are set
+ * in mask[0 .. n_words) (host array, read during the call; bit i of word w:
+ * mask position 32 w + i of the current device); default priority.  The
+ * runtime deals consecutive mask positions out to the XCDs in turn, and fails
+ * (SPDE_EHIP) for a mask that leaves an XCD with no compute unit.  For a server
+ * that keeps some compute units free of its long kernels, so that short kernels
+ * on other streams start at once.  Results do not depend on the mask, only
+ * speed.  n_words in [1, 64], stream_out non-null, mask not all zero, else
+ * SPDE_EINVAL.  The caller owns the stream: spde_stream_destroy releases it,
+ * once no work, event or memory pool refers to it any more. */
+spde_status spde_stream_create_cu_mask(int n_words, const uint32_t* mask, void** stream_out);
+spde_status spde_stream_destroy(void* stream);
+
 /* Autotuning of the multigrid tile shapes (default on).  When on, the first
  * sample or V-cycle call of a handle times every admissible tile shape of each
  * per-level kernel at max_batch and keeps the fastest; the choice is shared by

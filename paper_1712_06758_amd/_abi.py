@@ -32,6 +32,8 @@ SIGNATURES = {
                                       _i64p]),
     "spde_set_transfer": (C.c_int, [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp]),
     "spde_set_refinement": (C.c_int, [_vp, C.c_double, C.c_int]),
+    "spde_stream_create_cu_mask": (C.c_int, [C.c_int, _vp, C.POINTER(_vp)]),
+    "spde_stream_destroy": (C.c_int, [_vp]),
     "spde_build_transfer_device_rows": (C.c_int, [C.c_int, C.c_int64, _vp, C.c_int64, _vp, _vp, _i64p, _vp]),
     "spde_build_transfer_device_fill": (C.c_int, [C.c_int, C.c_int64, _vp, C.c_int64, _vp, _vp, _vp, _vp, _vp]),
     "spde_transfer_coarsen": (C.c_int, [C.c_int, C.c_int64, _vp, _vp, _vp, C.POINTER(_i64p),

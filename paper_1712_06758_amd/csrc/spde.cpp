@@ -1338,6 +1338,23 @@ spde_status spde_set_transfer_order(spde_handle h, const int32_t* order_dev) {
   return SPDE_OK;
 }
 
+spde_status spde_stream_create_cu_mask(int n_words, const uint32_t* mask, void** stream_out) {
+  if (n_words < 1 || n_words > 64 || !mask || !stream_out) return fail(SPDE_EINVAL, "invalid CU mask");
+  uint32_t any = 0;
+  for (int w = 0; w < n_words; ++w) any |= mask[w];
+  if (!any) return fail(SPDE_EINVAL, "the CU mask selects no compute unit");
+  hipStream_t st = nullptr;
+  HIPCHK(hipExtStreamCreateWithCUMask(&st, (uint32_t)n_words, mask));
+  *stream_out = (void*)st;
+  return SPDE_OK;
+}
+
+spde_status spde_stream_destroy(void* stream) {
+  if (!stream) return fail(SPDE_EINVAL, "null stream");
+  HIPCHK(hipStreamDestroy((hipStream_t)stream));
+  return SPDE_OK;
+}
+
 spde_status spde_set_split(spde_handle h, int ways) {
   Ctx* c = reinterpret_cast<Ctx*>(h);
   if (!c) return fail(SPDE_EINVAL, "null handle");

@@ -23,6 +23,7 @@ CPU with a simulated engine (tests/test_serve.py).
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import json
 import math
 import sys
@@ -96,7 +97,8 @@ class GpuEngine:
 
     STATE_ACTIVE, STATE_DONE, STATE_NOTCONV, STATE_FAILED, STATE_IDLE = 0, 1, 2, 3, 4
 
-    def __init__(self, n, kappa, g, precision, slots, device, rtol=None, meshes=None, poll=4, transfers=None):
+    def __init__(self, n, kappa, g, precision, slots, device, rtol=None, meshes=None, poll=4, transfers=None,
+                 cu_mask=None):
         import torch
         from . import Box
         self.torch = torch
@@ -106,7 +108,10 @@ class GpuEngine:
         self.box = Box(n, kappa, g, precision=precision, rtol=rtol, max_batch=slots, device=device)
         self.box.set_poll_interval(poll)
         self.poll_iters = poll
-        self.stream = torch.cuda.Stream(device=device)
+        if cu_mask is None:
+            self.stream = torch.cuda.Stream(device=device)
+        else:   # a stream confined to the compute units of the mask
+            self.stream = masked_stream(device, cu_mask, n)
         self.free = list(range(slots - 1, -1, -1))
         self.busy = {}
         self.transfers = {}           # mesh name -> (n_tet, nnz, rp, ci, cv)
@@ -124,7 +129,6 @@ class GpuEngine:
         self._event = None
 
     def _sp(self):
-        import ctypes as C
         return C.c_void_p(self.stream.cuda_stream)
 
     def add_mesh(self, name, xyz, tets):
@@ -391,13 +395,55 @@ class Server:
 # the GPU.  (More slots on the small levels raise the sustainable request rate
 # at the cost of latency.)
 DEFAULT_SLOTS = {16: 128, 32: 128, 64: 64, 128: 16, 256: 4}
+# compute units kept free of the 128^3 / 256^3 engines' kernels (4 per XCD of 256)
+DEFAULT_RESERVE_CUS = 32
+
+
+_MASKED_STREAMS = {}
+
+
+def masked_stream(device, cu_mask, tag):
+    """A stream whose kernels run only on the compute units of cu_mask (bit i of
+    word w: unit 32 w + i), one per (device, mask, tag) for the life of the
+    process, like torch's own stream pool: tensors whose memory was last used on
+    it (results, noise marked with record_stream) may outlive any engine."""
+    import torch
+    words = np.ascontiguousarray(cu_mask, dtype=np.uint32)
+    device = torch.device(device)
+    key = (device.index, words.tobytes(), tag)
+    st = _MASKED_STREAMS.get(key)
+    if st is None:
+        ptr = C.c_void_p()
+        with torch.cuda.device(device):
+            _abi.check(_abi.lib().spde_stream_create_cu_mask(words.size, words.ctypes.data, C.byref(ptr)))
+        st = _MASKED_STREAMS[key] = torch.cuda.ExternalStream(ptr.value, device=device)
+    return st
+
+
+def big_level_cu_mask(n_cu, reserve):
+    """CU mask words for the long-kernel engines: the first n_cu - reserve mask
+    bits set.  The runtime deals consecutive mask bits out to the XCDs in turn
+    (it rejects a mask that leaves one XCD with no compute unit), so the top
+    bits are the last compute units of every XCD: with reserve a multiple of 8
+    each XCD keeps reserve / 8 of its units for the short kernels of the small
+    levels."""
+    if not 0 < reserve < n_cu:
+        raise ValueError(f"reserve must lie in (0, {n_cu})")
+    words = np.zeros((n_cu + 31) // 32, dtype=np.uint32)
+    for i in range(n_cu - reserve):
+        words[i // 32] |= np.uint32(1 << (i % 32))
+    return words
 
 
 def build_gpu_server(levels=(32, 64, 128, 256), corr_len=0.05, precision="mixed", slots=None,
-                     hbm_budget=None, device=None, keep_results=False, poll=4, noise_seed=2024):
+                     hbm_budget=None, device=None, keep_results=False, poll=4, noise_seed=2024,
+                     reserve_cus=DEFAULT_RESERVE_CUS, big_level=128):
     """Engines for the levels and their coupled coarse boxes.  A request's noise
     is the generator field of (noise_seed, request_event(request seed)); its
-    coarse part draws the restriction of that field."""
+    coarse part draws the restriction of that field.  reserve_cus > 0: the
+    engines of boxes of big_level^3 and above run on streams that leave that many
+    compute units to the smaller boxes, whose kernels then need not wait for a
+    long kernel to finish."""
     import torch
     from . import coarsen_transfer_host, g_unit_variance
     from workloads import serve_mesh
@@ -409,6 +455,10 @@ def build_gpu_server(levels=(32, 64, 128, 256), corr_len=0.05, precision="mixed"
     slots = slots or {n: DEFAULT_SLOTS.get(n, 8) for n in sizes}
     engines = {}
     meshes = {n: serve_mesh(n) for n in levels}
+    big_mask = None
+    if reserve_cus > 0:
+        n_cu = torch.cuda.get_device_properties(device).multi_processor_count
+        big_mask = big_level_cu_mask(n_cu, reserve_cus)
     # finest first: the coarse part of level n projects with Pi of the (n/2)^3 box
     # onto level n's mesh, coarsened from the fine engine's Pi (children summed,
     # eq. recursive_l2_projection) instead of clipped again
@@ -418,7 +468,7 @@ def build_gpu_server(levels=(32, 64, 128, 256), corr_len=0.05, precision="mixed"
         if 2 * n in levels:
             coarse[2 * n] = coarsen_transfer_host(2 * n, *engines[2 * n].host_transfers[2 * n])
         engines[n] = GpuEngine(n, kappa, g, precision, slots[n], device, meshes=need, poll=poll,
-                               transfers=coarse)
+                               transfers=coarse, cu_mask=big_mask if n >= big_level else None)
         if 2 * n in engines:
             engines[2 * n].host_transfers.clear()     # device copies are registered
     if hbm_budget is None:
@@ -440,6 +490,8 @@ def main(argv=None):
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--levels", default="32,64,128,256")
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--reserve-cus", type=int, default=DEFAULT_RESERVE_CUS,
+                    help="compute units kept free of the 128^3 and 256^3 engines' kernels (0: none)")
     ap.add_argument("--slots", default="",
                     help="slots per box size overriding the defaults, e.g. 32:512,64:128,256:8")
     args = ap.parse_args(argv)
@@ -451,7 +503,7 @@ def main(argv=None):
         over = {int(k): int(v) for k, v in (item.split(":") for item in args.slots.split(","))}
         sizes = sorted(set(levels) | {n // 2 for n in levels if n != min(levels)})
         slots = {n: over.get(n, DEFAULT_SLOTS.get(n, 8)) for n in sizes}
-    srv = build_gpu_server(levels, SERVE_CORR_LEN, args.precision, slots=slots)
+    srv = build_gpu_server(levels, SERVE_CORR_LEN, args.precision, slots=slots, reserve_cus=args.reserve_cus)
     # warm-up: one request per level, not timed
     warm = [(0.0, n, 10 ** 6 + i) for i, n in enumerate(levels)]
     srv.run(warm)

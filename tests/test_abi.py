@@ -253,3 +253,19 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+def test_stream_create_cu_mask_validation(lib):
+    import ctypes as C
+    import numpy as np
+    from paper_1712_06758_amd import _abi
+    L = _abi.lib()
+    out = C.c_void_p()
+    w = np.zeros(8, dtype=np.uint32)
+    assert L.spde_stream_create_cu_mask(8, w.ctypes.data, C.byref(out)) == -1      # selects no unit
+    w[:] = 0xFFFFFFFF
+    assert L.spde_stream_create_cu_mask(0, w.ctypes.data, C.byref(out)) == -1
+    assert L.spde_stream_create_cu_mask(65, w.ctypes.data, C.byref(out)) == -1
+    assert L.spde_stream_create_cu_mask(8, None, C.byref(out)) == -1
+    assert L.spde_stream_create_cu_mask(8, w.ctypes.data, None) == -1
+    assert L.spde_stream_destroy(None) == -1

@@ -25,7 +25,11 @@ def test_alone_equals_mix_and_oracle():
     assert rep["completed"] == len(arr)
     mix = {r.seed: r for r in srv.done}
     logged = sorted(mix)[:: max(1, len(mix) // 10)][:10]
-    alone = build_gpu_server(levels, 0.05, "fp64", slots={32: 8, 64: 4}, keep_results=True, poll=2)
+    # alone, and with the 64^3 engine on a stream confined to 224 of the 256 compute
+    # units: where the blocks run does not change a bit of the result
+    alone = build_gpu_server(levels, 0.05, "fp64", slots={32: 8, 64: 4}, keep_results=True, poll=2,
+                             reserve_cus=32, big_level=64)
+    assert alone.engines[64].stream is not alone.engines[32].stream
     for i, seed in enumerate(logged):
         alone.run([(0.0, seed[0], seed[1])], time_limit=60)
         a = alone.done[-1]

@@ -149,3 +149,17 @@ def test_report_fields():
         lv = rep["levels"][n]
         assert lv["requests"] == 5 and lv["p99_ms"] >= lv["p50_ms"] > 0
     assert rep["samples_per_s"] > 0
+
+
+def test_big_level_cu_mask_keeps_every_xcd_populated():
+    from paper_1712_06758_amd.serve import big_level_cu_mask
+    w = big_level_cu_mask(256, 32)
+    assert w.dtype == np.uint32 and w.size == 8
+    bits = np.unpackbits(w.view(np.uint8), bitorder="little")
+    assert bits.sum() == 224 and bits[:224].all() and not bits[224:].any()
+    # mask bits go to the 8 XCDs in turn: each keeps 28 units and frees 4
+    assert all(bits[x::8].sum() == 28 for x in range(8))
+    with pytest.raises(ValueError):
+        big_level_cu_mask(256, 0)
+    with pytest.raises(ValueError):
+        big_level_cu_mask(256, 256)
