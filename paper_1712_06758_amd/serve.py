@@ -154,7 +154,6 @@ class GpuEngine:
     def start(self, part, xi):
         """Start `part` in a free slot from a noise tensor [n^3] on the device or
         from a NoiseKey (noise drawn inside the initialisation kernel)."""
-        import ctypes as C
         slot = self.free.pop()
         part.slot = slot
         self.busy[slot] = part
@@ -199,7 +198,6 @@ class GpuEngine:
 
     def finish(self, part, mesh):
         """Field of a finished part projected onto `mesh`; frees the slot."""
-        import ctypes as C
         torch = self.torch
         L = _abi.lib()
         n_tet, nnz, rp, ci, cv, od = self.transfers[mesh]
