@@ -198,7 +198,11 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev,
  * [rtol, 0.5]), so the result has the accuracy of a cold solve.  iters_host
  * counts the correction solve's iterations.  White noise puts most of the load
  * at the grid scale, which the coarse field cannot represent, so the start
- * saves few iterations (measured: under one at these sizes). */
+ * saves few iterations (measured: under one at these sizes).  u_coarse_dev is
+ * read only; it must hold batch (n/2)^3 values (not checked).  Errors as
+ * spde_sample, and SPDE_EINVAL if xi_dev or u_coarse_dev is NULL.  Iterative
+ * refinement (spde_set_refinement) follows the correction solve as in
+ * spde_sample. */
 spde_status spde_sample_warm(spde_handle h, int batch, const double* xi_dev, const double* u_coarse_dev,
                              double* u_tet_dev, double* u_box_dev, double* sigma_dev, void* stream,
                              int* iters_host, double* relres_host);
@@ -367,8 +371,8 @@ spde_status spde_set_face_preconditioner(spde_handle h, int kind);
  * [rtol, 0.5].  This lets the mixed
  * precision (float32 multigrid) reach residuals far below its rtol.
  * target = 0 (default) turns refinement off; target in [0, 1), max_passes in
- * [0, 16].  Applies to spde_sample and spde_sample_seeded (not to the
- * continuous-batching slots).  relres_host then reports the final residual at
+ * [0, 16].  Applies to spde_sample, spde_sample_seeded and spde_sample_warm
+ * (not to the continuous-batching slots).  relres_host then reports the final residual at
  * no extra cost; a sample may stay above the target when max_passes runs out. */
 spde_status spde_set_refinement(spde_handle h, double target, int max_passes);
 
