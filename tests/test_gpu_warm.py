@@ -52,3 +52,24 @@ def test_warm_start_from_the_coupled_coarse_solution(torch_cuda, prec, bar):
     # iteration count by little either way (its tolerance scales with the
     # 2-norm of r0, the cold solve stops on the preconditioned norm)
     assert int(warm["iters"].max()) <= int(cold["iters"].max()) + 3
+
+
+def test_warm_start_with_refinement(torch_cuda):
+    """Mixed precision, warm start, then float64 refinement passes: the true
+    residual meets the refinement target and the field meets the fp64 bar."""
+    torch = torch_cuda
+    n, kappa = 32, 10.0
+    g = gval(kappa)
+    xi = xi_batch(n, [31, 32])
+    xc = np.stack([N.restrict(n, x) for x in xi])
+    uc = oracle_u(n // 2, kappa, g, xc)
+    ref = oracle_u(n, kappa, g, xi)
+    say(f"warm start + refinement mixed n={n}")
+    box = P().Box(n, kappa, precision="mixed", max_batch=2)
+    box.set_refinement(1e-11, max_passes=3)
+    out = box.sample_warm(torch.tensor(xi, device="cuda"), torch.tensor(uc, device="cuda"), u_box=True,
+                          relres=True)
+    err = max(rel_l2(out["u_box"][b].cpu().numpy(), ref[b]) for b in range(2))
+    say(f"  iters {out['iters'].tolist()} relres {out['relres'].max():.2e} err {err:.2e}")
+    assert out["relres"].max() <= 1e-11
+    assert err <= 1e-10
