@@ -159,3 +159,28 @@ def test_pipelined_up_kernel_each_face_kind_with_cell_coefficients(torch_cuda, k
     errs = [rel_l2(u[b], R["u"][b]) for b in range(2)]
     say(f"  iters {out['iters'].tolist()} errs {errs}")
     assert max(errs) <= (1e-10 if prec == "fp64" else 1e-7)
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-10), ("mixed", 1e-7)])
+def test_warm_start_with_cell_coefficients(torch_cuda, prec, bar):
+    """Warm start from a coarse solution of the Galerkin coarse problem (kappa^2
+    averaged over the children, the restricted noise): the cell-wise residual
+    pass and the correction solve reach the fine oracle field."""
+    from oracle import noise as N
+    say(f"variable coefficients, warm start n=16 {prec}")
+    torch = torch_cuda
+    n = 16
+    kc = smooth_field(n, 5.0, 40.0, 51)
+    gc = smooth_field(n, 1.0, 4.0, 52)
+    xi = xi_batch(n, [61, 62])
+    kcc = V.coarse_kappa(n, kc)
+    uc = V.solve_u_batch(n // 2, kcc, np.full((n // 2) ** 3, gc.mean()), np.stack([N.restrict(n, x) for x in xi]))
+    box = P().Box(n, 10.0, precision=prec, max_batch=2)
+    box.set_coefficients(kc, gc)
+    out = box.sample_warm(torch.tensor(xi, device="cuda"), torch.tensor(uc, device="cuda"), u_box=True,
+                          relres=True)
+    ref = V.solve_u_batch(n, kc, gc, xi)
+    errs = [rel_l2(out["u_box"][b].cpu().numpy(), ref[b]) for b in range(2)]
+    say(f"  iters={out['iters'].tolist()} errs={errs} relres={out['relres']}")
+    assert max(errs) <= bar
+    assert out["relres"].max() <= (1e-9 if prec == "fp64" else 1e-6)
