@@ -31,10 +31,14 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources and the compiler flags they are built with:
+    the counter-measured traffic in profiles/ holds only for that build."""
     h = hashlib.sha256()
     for f in ("spde_kernels.hip", "spde_vcycle.inc", "spde_launch.inc", "spde_internal.h"):
         with open(os.path.join(ROOT, "paper_1712_06758_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    from paper_1712_06758_amd.build import FLAGS
+    h.update(" ".join(FLAGS).encode())
     return h.hexdigest()[:16]
 
 

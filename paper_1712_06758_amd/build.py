@@ -21,6 +21,9 @@ FLAGS = [
     f"--offload-arch={ARCH}",
     # no packed fp32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the register-pressure trackers of the AMDGPU scheduler: the float fine
+    # up-kernels spill 8 instead of 16 B per lane and run 3 % faster
+    "-mllvm", "-amdgpu-use-amdgpu-trackers=1",
     "-Wno-unused-command-line-argument",
 ]
 
