@@ -34,7 +34,6 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import _abi
-from ._abi import SPDE_OK
 
 
 # ---------------------------------------------------------------------------
