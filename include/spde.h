@@ -199,13 +199,14 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev,
  * counts the correction solve's iterations.  White noise puts most of the load
  * at the grid scale, which the coarse field cannot represent, so the start
  * saves few iterations (measured: under one at these sizes).  u_coarse_dev is
- * read only; it must hold batch (n/2)^3 values (not checked).  Errors as
- * spde_sample, and SPDE_EINVAL if xi_dev or u_coarse_dev is NULL.  Iterative
- * refinement (spde_set_refinement) follows the correction solve as in
- * spde_sample. */
+ * read only; u_coarse_count is the number of float64 values the caller passes
+ * there and must equal batch (n/2)^3.  Errors as spde_sample, and SPDE_EINVAL
+ * if xi_dev or u_coarse_dev is NULL or u_coarse_count is not batch (n/2)^3.
+ * Iterative refinement (spde_set_refinement) follows the correction solve as
+ * in spde_sample. */
 spde_status spde_sample_warm(spde_handle h, int batch, const double* xi_dev, const double* u_coarse_dev,
-                             double* u_tet_dev, double* u_box_dev, double* sigma_dev, void* stream,
-                             int* iters_host, double* relres_host);
+                             int64_t u_coarse_count, double* u_tet_dev, double* u_box_dev,
+                             double* sigma_dev, void* stream, int* iters_host, double* relres_host);
 
 /* Noise of the coupled coarse sample (eq. ml-linsys, F_{l+1} = P^T F_l):
  * xi_c[I] = 8^{-1/2} * sum of xi_f over the 8 children of coarse cell I.

@@ -64,11 +64,6 @@ def solve_schur(n: int, kappa: float, rhs_cells: np.ndarray) -> np.ndarray:
     return _inv(_fwd(rhs_cells, n) / schur_eigs(n, kappa), n)
 
 
-def apply_schur(n: int, kappa: float, u: np.ndarray) -> np.ndarray:
-    """S u through the spectral form."""
-    return _inv(_fwd(u, n) * schur_eigs(n, kappa), n)
-
-
 def solve_u(n: int, kappa: float, g: float, xi: np.ndarray) -> np.ndarray:
     """Cell field u of the mixed system for one noise vector xi (length n^3)."""
     h = 1.0 / n

@@ -327,7 +327,8 @@ class Box:
         B = xi.shape[0]
         _check_dev_f64(xi, (B, self.n ** 3), "xi")
         _check_dev_f64(u_coarse, (B, (self.n // 2) ** 3), "u_coarse")
-        return self._run(B, lambda *a: _abi.lib().spde_sample_warm(self._hh.h, B, _ptr(xi), _ptr(u_coarse), *a),
+        return self._run(B, lambda *a: _abi.lib().spde_sample_warm(self._hh.h, B, _ptr(xi), _ptr(u_coarse),
+                                                                   u_coarse.numel(), *a),
                          u_tet, u_box, sigma, relres, allow_notconv)
 
     def sample_seeded(self, seed: int, event0: int = 0, batch: int = 1, coupled: bool = False, u_tet=True,

@@ -40,7 +40,7 @@ SIGNATURES = {
                                         C.POINTER(C.POINTER(C.c_int32)), C.POINTER(C.POINTER(C.c_double)),
                                         _i64p]),
     "spde_sample": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
-    "spde_sample_warm": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "spde_sample_warm": (C.c_int, [_vp, C.c_int, _vp, _vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "spde_restrict_noise": (C.c_int, [C.c_int, C.c_int, _vp, _vp, _vp]),
     "spde_sample_seeded": (C.c_int, [_vp, C.c_int, C.c_uint64, C.c_uint64, C.c_int, _vp, _vp, _vp, _vp, _vp,
                                      _vp]),

@@ -988,9 +988,10 @@ spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_de
   bool notconv = false, failed = false;
   int most = 0;
   std::vector<int> total(batch, 0);
+  std::vector<char> bad(batch, 0);   // samples that failed: excluded from refinement
   for (int b = 0; b < batch; ++b) {
     const Scalars& sc = c->host_sc[b];
-    if (sc.state == ST_FAILED) failed = true;
+    if (sc.state == ST_FAILED) { failed = true; bad[b] = 1; }
     if (sc.state == ST_ACTIVE || (sc.flags & FL_NOTCONV)) notconv = true;
     total[b] = sc.state == ST_ACTIVE ? launched : sc.iters;
     if (sc.state == ST_FINISH || sc.state == ST_DONE) most = std::max(most, sc.iters);
@@ -1001,30 +1002,32 @@ spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_de
   // Iterative refinement in float64: with r = F - A U (flux recovered from U,
   // so only the cell row is nonzero), solve A d = r by the same MINRES and set
   // U += d, for the samples whose relative true residual exceeds the target.
+  // A failed sample (its field is NaN) is left out of every pass; the others
+  // are refined as if it were not in the batch.
   bool res_final = false;   // host_res holds the residual of the current U
-  if (c->refine_target > 0.0 && !failed) {
+  if (c->refine_target > 0.0) {
     for (int pass = 0;; ++pass) {
       s = residual();
       if (s != SPDE_OK) return s;
       res_final = true;
+      std::vector<char> refine(batch, 0);
       bool need_any = false;
       double worst = 0.0;
       for (int b = 0; b < batch; ++b) {
-        if (!(c->host_res[b] <= c->refine_target)) {
-          need_any = true;
-          worst = std::max(worst, c->host_res[b]);
-        }
+        if (bad[b] || c->host_res[b] <= c->refine_target) continue;
+        refine[b] = 1;
+        need_any = true;
+        if (std::isfinite(c->host_res[b])) worst = std::max(worst, c->host_res[b]);
       }
       if (!need_any || pass >= c->refine_max) break;
       // the pass has to reduce its residual by target / worst only (a factor
       // of 10 to spare); never tighter than the configured rtol, which the
       // preconditioned MINRES is known to reach
-      const double tol_pass = std::isfinite(worst) && worst > 0.0
-                                  ? std::min(0.5, std::max(c->rtol, 0.1 * c->refine_target / worst))
-                                  : c->rtol;
+      const double tol_pass = worst > 0.0 ? std::min(0.5, std::max(c->rtol, 0.1 * c->refine_target / worst))
+                                          : c->rtol;
       HIPCHK(launch_init_correction(c->F, bx, batch, tol_pass, c->max_iter, st));
       for (int b = 0; b < batch; ++b)
-        if (c->host_res[b] <= c->refine_target) HIPCHK(launch_set_state(c->F.sc, b, 1, ST_DONE, st));
+        if (!refine[b]) HIPCHK(launch_set_state(c->F.sc, b, 1, ST_DONE, st));
       if (split) {   // the second stream's half starts after the pass's set-up
         HIPCHK(hipEventRecord(c->ev_fork, st));
         HIPCHK(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0));
@@ -1032,16 +1035,20 @@ spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_de
       int lp = 0;
       s = iterate(0, lp);
       if (s != SPDE_OK) return s;
+      bool more = false;
       for (int b = 0; b < batch; ++b) {
+        if (!refine[b]) continue;   // not refined in this pass
         const Scalars& sc = c->host_sc[b];
-        if (c->host_res[b] <= c->refine_target) continue;   // not refined in this pass
-        if (sc.state == ST_FAILED) failed = true;
+        if (sc.state == ST_FAILED) { failed = true; bad[b] = 1; }
+        else more = true;
         if (sc.state == ST_ACTIVE || (sc.flags & FL_NOTCONV)) notconv = true;
         total[b] += sc.state == ST_ACTIVE ? lp : sc.iters;
       }
+      // samples that failed in this pass get a NaN field; the others keep
+      // their refined iterate
       HIPCHK(launch_fix_solution(c->F, bx, batch, 0, st));
       res_final = false;
-      if (failed) break;
+      if (!more) break;
     }
   }
   if (iters_host)
@@ -1092,11 +1099,15 @@ spde_status spde_sample(spde_handle h, int batch, const double* xi_dev, double* 
 }
 
 spde_status spde_sample_warm(spde_handle h, int batch, const double* xi_dev, const double* u_coarse_dev,
-                             double* u_tet_dev, double* u_box_dev, double* sigma_dev, void* stream, int* iters_host,
-                             double* relres_host) {
+                             int64_t u_coarse_count, double* u_tet_dev, double* u_box_dev, double* sigma_dev,
+                             void* stream, int* iters_host, double* relres_host) {
   Ctx* c = reinterpret_cast<Ctx*>(h);
   if (!c) return fail(SPDE_EINVAL, "null handle");
   if (!xi_dev || !u_coarse_dev) return fail(SPDE_EINVAL, "xi or u_coarse is null");
+  const int64_t mc = c->n / 2;
+  if (batch >= 1 && u_coarse_count != (int64_t)batch * mc * mc * mc)
+    return fail(SPDE_EINVAL, "u_coarse holds %lld values, %d samples of (n/2)^3 = %lld need %lld",
+                (long long)u_coarse_count, batch, (long long)(mc * mc * mc), (long long)(batch * mc * mc * mc));
   NoiseSrc src;
   src.xi = xi_dev;
   return sample_impl(c, batch, src, u_tet_dev, u_box_dev, sigma_dev, stream, iters_host, relres_host, u_coarse_dev);

@@ -180,6 +180,20 @@ hipError_t launch_mg_up(bool fp64, int shape, bool fine, const void* b0, const v
                         void* o1, const Level& L, int batch, const Scalars* sc, const double* vs0,
                         const double* vs1, double* part, const Box& bx, hipStream_t st);
 hipError_t prepare_coarse(bool fp64, size_t lds_bytes);
+// the same per level precision (spde_mg_f32.hip / spde_mg_f64.hip)
+#define SPDE_MG_DECL(NAME)                                                                                      \
+  hipError_t launch_mg_down_##NAME(int shape, bool fine, const void* b0, const void* b1, void* rH,            \
+                                   const Level& L, int batch, const Scalars* sc, hipStream_t st);             \
+  hipError_t launch_mg_up_##NAME(int shape, bool fine, const void* b0, const void* b1, const void* eH,        \
+                                 void* o0, void* o1, const Level& L, int batch, const Scalars* sc,            \
+                                 const double* vs0, const double* vs1, double* part, const Box& bx,           \
+                                 hipStream_t st);                                                             \
+  hipError_t prepare_coarse_##NAME(size_t lds_bytes);                                                         \
+  hipError_t launch_mg_coarse_##NAME(const void* btop, void* etop, const CoarseParams& P, size_t lds_bytes,   \
+                                     int batch, const Scalars* sc, hipStream_t st);
+SPDE_MG_DECL(f32)
+SPDE_MG_DECL(f64)
+#undef SPDE_MG_DECL
 hipError_t launch_mg_coarse(bool fp64, const void* btop, void* etop, const CoarseParams& P, size_t lds_bytes,
                             int batch, const Scalars* sc, hipStream_t st);
 hipError_t launch_scalar(const Fields& F, int nb_up, int nb_pb, int batch, hipStream_t st);

@@ -19,157 +19,9 @@
 //                                      convergence test
 //   operator                         : v_{j+1} = A z_j - (delta/gamma) v_j - (gamma/gamma_prev) v_{j-1}
 //                                      and the delayed w/x update of step j-1
-#include "spde_internal.h"
+#include "spde_common.inc"
 
 namespace spde {
-
-// ---------------------------------------------------------------------------
-// helpers
-
-// Blocks are dispatched round-robin over the 8 XCDs of the MI355X; give each
-// XCD a contiguous range of logical blocks so that stencil neighbours share
-// that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
-  if (nblocks & 7) return bid;
-  const int per = nblocks >> 3;
-  return (bid & 7) * per + (bid >> 3);
-}
-
-// Sum over the block; the result is valid in thread 0.  Fixed order.
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
-  __syncthreads();
-  return r;
-}
-
-__device__ __forceinline__ int nnbr(int x, int y, int z, int m) {
-  return (x > 0) + (x < m - 1) + (y > 0) + (y < m - 1) + (z > 0) + (z < m - 1);
-}
-
-// Diagonal d = k2 + a * (number of neighbours) of S~ and its reciprocal.  Only
-// cells on the box boundary have fewer than 6 neighbours; interior cells take
-// the precomputed reciprocal, boundary cells divide.
-template <typename TM>
-struct Diag {
-  TM k2, a, d6, id6;
-  __device__ __forceinline__ Diag(double k2_, double a_)
-      : k2((TM)k2_), a((TM)a_), d6((TM)(k2_ + 6.0 * a_)), id6((TM)(1.0 / (k2_ + 6.0 * a_))) {}
-  __device__ __forceinline__ TM d(int nn) const { return nn == 6 ? d6 : k2 + a * (TM)nn; }
-  __device__ __forceinline__ TM inv(int nn) const { return nn == 6 ? id6 : (TM)1 / (k2 + a * (TM)nn); }
-};
-
-// ---------------------------------------------------------------------------
-// Face block of the preconditioner.
-//
-// On the interior faces of one grid line M = (1/q)(I + S), with q = 3/(2h^3)
-// and (S v)_g = (v_{g-1} + v_{g+1}) / 4 (boundary faces carry no unknown and
-// read as 0).  The face block of P^-1 is either diag(M)^-1 = q I, or the
-// truncated Neumann series q (I - S + S^2) of M^-1, which is symmetric
-// positive definite (eigenvalues of S lie in (-1/2, 1/2)) and needs no pass
-// of its own: along each line M P^-1 = I + S (diagonal) or I + S^3 (series).
-//
-// Given w[k] = v_{f+k}, k = -3..3 (f the low face of a cell, i its index along
-// the line, faces outside 1..n-1 zero), line_terms returns
-//   mz  = (M P^-1 v)_f,   zf = (P^-1 v)_f / q,   zh = (P^-1 v)_{f+1} / q.
-
-template <int R>
-__device__ __forceinline__ void line_load(const double* __restrict__ v, int64_t c, int64_t stride, int i, int n,
-                                          double* w) {
-#pragma unroll
-  for (int k = -3; k <= 3; ++k) {
-    const int g = i + k;
-    w[k + 3] = (k >= -R && k <= R && g >= 1 && g <= n - 1) ? v[c + k * stride] : 0.0;
-  }
-}
-
-__device__ __forceinline__ void line_terms(const double* w, int i, int n, int poly, double& mz, double& zf,
-                                           double& zh) {
-  if (!poly) {
-    mz = w[3] + 0.25 * (w[2] + w[4]);
-    zf = w[3];
-    zh = w[4];
-    return;
-  }
-  if (i >= 4 && i <= n - 4) {
-    // all faces f-3..f+3 interior: the series collapses to fixed stencils
-    //   (P^-1 v)_f / q = 9/8 v_f - (v_{f-1} + v_{f+1}) / 4 + (v_{f-2} + v_{f+2}) / 16
-    //   (M P^-1 v)_f   = v_f + (v_{f-3} + v_{f+3} + 3 (v_{f-1} + v_{f+1})) / 64
-    const double a = w[2] + w[4];
-    zf = 1.125 * w[3] - 0.25 * a + 0.0625 * (w[1] + w[5]);
-    zh = 1.125 * w[4] - 0.25 * (w[3] + w[5]) + 0.0625 * (w[2] + w[6]);
-    mz = w[3] + 0.015625 * ((w[0] + w[6]) + 3.0 * a);
-    return;
-  }
-  double s1[7], s2[7];
-#pragma unroll
-  for (int j = 1; j <= 5; ++j) {
-    const int g = i + j - 3;
-    s1[j] = (g >= 1 && g <= n - 1) ? 0.25 * (w[j - 1] + w[j + 1]) : 0.0;
-  }
-#pragma unroll
-  for (int j = 2; j <= 4; ++j) {
-    const int g = i + j - 3;
-    s2[j] = (g >= 1 && g <= n - 1) ? 0.25 * (s1[j - 1] + s1[j + 1]) : 0.0;
-  }
-  const bool fi = i >= 1, hi = i + 1 <= n - 1;
-  mz = w[3] + (fi ? 0.25 * (s2[2] + s2[4]) : 0.0);
-  zf = fi ? w[3] - s1[3] + s2[3] : 0.0;
-  zh = hi ? w[4] - s1[4] + s2[4] : 0.0;
-}
-
-// Per-cell contributions to gamma^2 = <P^-1 v, v> and delta gamma^2 =
-// <A P^-1 v, P^-1 v> (v = (v_sigma, v_u), P^-1 v = (.., zhat)) of the cell
-// with global index g, coordinates (x, y, z), on an n^3 box; vs is the slot's
-// face storage (three n^3 arrays), vu the cell value, zc = zhat at the cell.
-// The same contributions from line values already gathered (wx, wy, wz hold
-// v_{f+k}, k = -3..3, along x, y, z; zero outside the interior faces).
-__device__ __forceinline__ void gamma_delta_lines(const double* wx, const double* wy, const double* wz, int x, int y,
-                                                  int z, const Box& bx, double vu, double zc, double k2, double& gg,
-                                                  double& dg) {
-  const int n = bx.n;
-  const double* ws[3] = {wx, wy, wz};
-  const int idx[3] = {x, y, z};
-  double sv = 0.0, szm = 0.0, dv = 0.0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    double mz, zf, zh;
-    line_terms(ws[d], idx[d], n, bx.poly, mz, zf, zh);
-    sv += zf * ws[d][3];
-    szm += zf * mz;
-    dv += zh - zf;
-  }
-  gg += bx.q * sv + zc * vu;
-  dg += bx.q * szm + 2.0 * zc * bx.h2q * dv - k2 * zc * zc;
-}
-
-__device__ __forceinline__ void gamma_delta_terms(const double* __restrict__ vs, int64_t g, int x, int y, int z,
-                                                  const Box& bx, double vu, double zc, double k2, double& gg,
-                                                  double& dg) {
-  const int n = bx.n;
-  const int64_t nc = bx.nc;
-  const int idx[3] = {x, y, z};
-  const int64_t str[3] = {1, n, bx.n2};
-  double sv = 0.0, szm = 0.0, dv = 0.0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    double w[7], mz, zf, zh;
-    if (bx.poly) line_load<3>(vs + d * nc, g, str[d], idx[d], n, w);
-    else line_load<1>(vs + d * nc, g, str[d], idx[d], n, w);
-    line_terms(w, idx[d], n, bx.poly, mz, zf, zh);
-    sv += zf * w[3];      // (P^-1 v)_f v_f / q
-    szm += zf * mz;       // (P^-1 v)_f (M P^-1 v)_f / q
-    dv += zh - zf;        // (B P^-1 v)_cell / (h^2 q)
-  }
-  gg += bx.q * sv + zc * vu;
-  dg += bx.q * szm + 2.0 * zc * bx.h2q * dv - k2 * zc * zc;
-}
 
 // ---------------------------------------------------------------------------
 // initialisation: v_1 = F = [0; scale * xi], state reset
@@ -214,756 +66,6 @@ __global__ __launch_bounds__(kBlock) void k_init_correction(Fields F, Box bx, in
     init_scalars(F, slot, tol, max_iter);
     F.sc[slot].flags = FL_ACCUM;
   }
-}
-
-// ---------------------------------------------------------------------------
-// multigrid: smooth from zero + residual + restriction (one level, 3-D tile)
-//
-// With bhat = D^-1 b the degree-2 Chebyshev smoother from a zero guess is
-//   x = cA bhat + (cB / d) sum_nbr bhat,
-// and the restricted residual is r_H[I] = sum over the 8 children of
-//   d (bhat - x) + a sum_nbr x.
-// Every phase runs as a compile-time-unrolled batch per thread: all global
-// loads of the batch are issued before any is consumed.
-
-template <int BX, int BY>
-__device__ __forceinline__ void split3(int e, int& lx, int& ly, int& lz) {
-  lx = e % BX;
-  ly = (e / BX) % BY;
-  lz = e / (BX * BY);
-}
-
-__device__ __forceinline__ bool inside(int x, int y, int z, int m) {
-  return (unsigned)x < (unsigned)m && (unsigned)y < (unsigned)m && (unsigned)z < (unsigned)m;
-}
-
-// Load b on the tile grown by H cells (zero outside the box) as bhat = b / d.
-template <typename TM, typename TB, int BX, int BY, int BZ, int H>
-__device__ __forceinline__ void load_bhat(TM* sb, const TB* __restrict__ b, int x0, int y0, int z0, int m,
-                                          const Diag<TM>& D) {
-  constexpr int N = BX * BY * BZ, R = (N + kBlock - 1) / kBlock;
-  TB v[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int e = threadIdx.x + r * kBlock;
-    int lx, ly, lz;
-    split3<BX, BY>(e, lx, ly, lz);
-    const int gx = x0 + lx - H, gy = y0 + ly - H, gz = z0 + lz - H;
-    v[r] = 0;
-    if (e < N && inside(gx, gy, gz, m)) v[r] = b[gx + (int64_t)m * (gy + (int64_t)m * gz)];
-  }
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int e = threadIdx.x + r * kBlock;
-    if (e < N) {
-      int lx, ly, lz;
-      split3<BX, BY>(e, lx, ly, lz);
-      const int gx = x0 + lx - H, gy = y0 + ly - H, gz = z0 + lz - H;
-      sb[e] = inside(gx, gy, gz, m) ? (TM)v[r] * D.inv(nnbr(gx, gy, gz, m)) : (TM)0;
-    }
-  }
-}
-
-template <typename TM, typename TB, int TX, int TY, int TZ, bool FINE>
-__global__ __launch_bounds__(kBlock) void k_mg_down(const TB* __restrict__ b0, const TB* __restrict__ b1,
-                                                    TM* __restrict__ rH, Level L, int nb,
-                                                    const Scalars* __restrict__ sc) {
-  constexpr int BX = TX + 4, BY = TY + 4, BZ = TZ + 4;
-  constexpr int XX = TX + 2, XY = TY + 2, XZ = TZ + 2;
-  __shared__ TM sb[BX * BY * BZ];
-  __shared__ TM sx[XX * XY * XZ];
-  const int m = L.m;
-  const int tpx = (m + TX - 1) / TX, tpy = (m + TY - 1) / TY;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int slot = lb / nb, t = lb - slot * nb;
-  const TB* b = b0;
-  if (sc) {
-    if (sc[slot].state != ST_ACTIVE) return;
-    if (FINE && (sc[slot].it & 1)) b = b1;
-  }
-  b += (int64_t)slot * L.nc;
-  const int x0 = (t % tpx) * TX, y0 = ((t / tpx) % tpy) * TY, z0 = (t / (tpx * tpy)) * TZ;
-  const Diag<TM> D(L.k2, L.a);
-  const TM a = D.a, cA = (TM)L.cA, cB = (TM)L.cB;
-
-  load_bhat<TM, TB, BX, BY, BZ, 2>(sb, b, x0, y0, z0, m, D);
-  __syncthreads();
-  {
-    constexpr int N = XX * XY * XZ, R = (N + kBlock - 1) / kBlock;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int e = threadIdx.x + r * kBlock;
-      if (e >= N) break;
-      int lx, ly, lz;
-      split3<XX, XY>(e, lx, ly, lz);
-      const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
-      TM v = 0;
-      if (inside(gx, gy, gz, m)) {
-        const int s = (lx + 1) + BX * ((ly + 1) + BY * (lz + 1));
-        const TM sum = sb[s - 1] + sb[s + 1] + sb[s - BX] + sb[s + BX] + sb[s - BX * BY] + sb[s + BX * BY];
-        v = cA * sb[s] + cB * D.inv(nnbr(gx, gy, gz, m)) * sum;
-      }
-      sx[e] = v;
-    }
-  }
-  __syncthreads();
-  constexpr int CX = TX / 2, CY = TY / 2, CZ = TZ / 2;
-  constexpr int NC = CX * CY * CZ, RC = (NC + kBlock - 1) / kBlock;
-  const int mH = m >> 1;
-  TM* r = rH + (int64_t)slot * mH * mH * mH;
-#pragma unroll
-  for (int q = 0; q < RC; ++q) {
-    const int e = threadIdx.x + q * kBlock;
-    if (e >= NC) break;
-    int cx, cy, cz;
-    split3<CX, CY>(e, cx, cy, cz);
-    const int gcx = (x0 >> 1) + cx, gcy = (y0 >> 1) + cy, gcz = (z0 >> 1) + cz;
-    if (gcx >= mH || gcy >= mH || gcz >= mH) continue;
-    TM acc = 0;
-#pragma unroll
-    for (int ch = 0; ch < 8; ++ch) {
-      const int lx = 2 * cx + (ch & 1), ly = 2 * cy + ((ch >> 1) & 1), lz = 2 * cz + (ch >> 2);
-      const int s = (lx + 2) + BX * ((ly + 2) + BY * (lz + 2));
-      const int u = (lx + 1) + XX * ((ly + 1) + XY * (lz + 1));
-      const TM d = D.d(nnbr(x0 + lx, y0 + ly, z0 + lz, m));
-      const TM sum = sx[u - 1] + sx[u + 1] + sx[u - XX] + sx[u + XX] + sx[u - XX * XY] + sx[u + XX * XY];
-      acc += d * (sb[s] - sx[u]) + a * sum;
-    }
-    r[gcx + (int64_t)mH * (gcy + (int64_t)mH * gcz)] = acc;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// multigrid: prolongation + correction + post-smoothing (one level, 3-D tile)
-//
-// The pre-smoothed iterate is recomputed from b on the tile's halo (no stored
-// state), the coarse correction is piecewise-constant prolongation of e_H,
-// and the post-smoother applies the same Chebyshev polynomial to the residual:
-//   r = b - A x ; y = c0 D^-1 r ; out = x + c1 y + c2 D^-1 (r - A y).
-// The fine launch also accumulates, per block, the partial sums
-//   <zhat, v_u>  and  zhat^T A zhat  with zhat = (diag(M)^-1 v_sigma, zhat_u),
-// from which the scalar step forms gamma_j and delta_j.
-
-template <typename TM, typename TB, typename TO, int TX, int TY, int TZ, bool FINE, bool VAR = false>
-__global__ __launch_bounds__(kBlock) void k_mg_up(const TB* __restrict__ b0, const TB* __restrict__ b1,
-                                                  const TM* __restrict__ eH, TO* __restrict__ o0,
-                                                  TO* __restrict__ o1, Level L, int nb,
-                                                  const Scalars* __restrict__ sc,
-                                                  const double* __restrict__ vs0,
-                                                  const double* __restrict__ vs1,
-                                                  double* __restrict__ part, Box bxc) {
-  constexpr int BX = TX + 6, BY = TY + 6, BZ = TZ + 6;
-  constexpr int XX = TX + 4, XY = TY + 4, XZ = TZ + 4;
-  constexpr int YX = TX + 2, YY = TY + 2, YZ = TZ + 2;
-  __shared__ TM sb[BX * BY * BZ];
-  __shared__ TM sx[XX * XY * XZ];
-  __shared__ TM sy[YX * YY * YZ];
-  __shared__ double red[kBlock / 64];
-  const int m = L.m;
-  const int tpx = (m + TX - 1) / TX, tpy = (m + TY - 1) / TY;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int slot = lb / nb, t = lb - slot * nb;
-  const TB* b = b0;
-  TO* o = o0;
-  const double* vs = vs0;
-  if (sc) {
-    if (sc[slot].state != ST_ACTIVE) return;
-    if (FINE && (sc[slot].it & 1)) { b = b1; o = o1; vs = vs1; }
-  }
-  b += (int64_t)slot * L.nc;
-  o += (int64_t)slot * L.nc;
-  const int mH = m >> 1;
-  const TM* e = eH + (int64_t)slot * mH * mH * mH;
-  const int x0 = (t % tpx) * TX, y0 = ((t / tpx) % tpy) * TY, z0 = (t / (tpx * tpy)) * TZ;
-  const Diag<TM> D(L.k2, L.a);
-  const TM a = D.a, cA = (TM)L.cA, cB = (TM)L.cB;
-  const TM c0 = (TM)L.c0, c1 = (TM)L.c1, c2 = (TM)L.c2;
-
-  load_bhat<TM, TB, BX, BY, BZ, 3>(sb, b, x0, y0, z0, m, D);
-  {
-    // coarse corrections of the tile+2 region, loaded while bhat lands in LDS
-    constexpr int N = XX * XY * XZ, R = (N + kBlock - 1) / kBlock;
-    TM ev[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = threadIdx.x + r * kBlock;
-      int lx, ly, lz;
-      split3<XX, XY>(i, lx, ly, lz);
-      const int gx = x0 + lx - 2, gy = y0 + ly - 2, gz = z0 + lz - 2;
-      ev[r] = 0;
-      if (i < N && inside(gx, gy, gz, m))
-        ev[r] = e[(gx >> 1) + (int64_t)mH * ((gy >> 1) + (int64_t)mH * (gz >> 1))];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = threadIdx.x + r * kBlock;
-      if (i >= N) break;
-      int lx, ly, lz;
-      split3<XX, XY>(i, lx, ly, lz);
-      const int gx = x0 + lx - 2, gy = y0 + ly - 2, gz = z0 + lz - 2;
-      TM v = 0;
-      if (inside(gx, gy, gz, m)) {
-        const int s = (lx + 1) + BX * ((ly + 1) + BY * (lz + 1));
-        const TM sum = sb[s - 1] + sb[s + 1] + sb[s - BX] + sb[s + BX] + sb[s - BX * BY] + sb[s + BX * BY];
-        v = cA * sb[s] + cB * D.inv(nnbr(gx, gy, gz, m)) * sum + ev[r];
-      }
-      sx[i] = v;
-    }
-  }
-  __syncthreads();
-  {
-    constexpr int N = YX * YY * YZ, R = (N + kBlock - 1) / kBlock;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = threadIdx.x + r * kBlock;
-      if (i >= N) break;
-      int lx, ly, lz;
-      split3<YX, YY>(i, lx, ly, lz);
-      const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
-      TM v = 0;
-      if (inside(gx, gy, gz, m)) {
-        const int s = (lx + 2) + BX * ((ly + 2) + BY * (lz + 2));
-        const int u = (lx + 1) + XX * ((ly + 1) + XY * (lz + 1));
-        const TM sum = sx[u - 1] + sx[u + 1] + sx[u - XX] + sx[u + XX] + sx[u - XX * XY] + sx[u + XX * XY];
-        const int nn = nnbr(gx, gy, gz, m);
-        const TM rr = D.d(nn) * (sb[s] - sx[u]) + a * sum;
-        v = c0 * D.inv(nn) * rr;
-      }
-      sy[i] = v;
-    }
-  }
-  __syncthreads();
-  constexpr int NT = TX * TY * TZ, RT = (NT + kBlock - 1) / kBlock;
-  double p_zv = 0.0, p_azz = 0.0;
-#pragma unroll
-  for (int r = 0; r < RT; ++r) {
-    const int i = threadIdx.x + r * kBlock;
-    if (i >= NT) break;
-    int lx, ly, lz;
-    split3<TX, TY>(i, lx, ly, lz);
-    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-    if (!inside(gx, gy, gz, m)) continue;
-    const int s = (lx + 3) + BX * ((ly + 3) + BY * (lz + 3));
-    const int u = (lx + 2) + XX * ((ly + 2) + XY * (lz + 2));
-    const int w = (lx + 1) + YX * ((ly + 1) + YY * (lz + 1));
-    const int nn = nnbr(gx, gy, gz, m);
-    const TM d = D.d(nn);
-    const TM sxn = sx[u - 1] + sx[u + 1] + sx[u - XX] + sx[u + XX] + sx[u - XX * XY] + sx[u + XX * XY];
-    const TM syn = sy[w - 1] + sy[w + 1] + sy[w - YX] + sy[w + YX] + sy[w - YX * YY] + sy[w + YX * YY];
-    const TM rr = d * (sb[s] - sx[u]) + a * sxn;
-    const TM t2 = rr - (d * sy[w] - a * syn);
-    const TM out = sx[u] + c1 * sy[w] + c2 * D.inv(nn) * t2;
-    const int64_t g = gx + (int64_t)m * (gy + (int64_t)m * gz);
-    const TO zo = (TO)out;
-    o[g] = zo;
-    if (FINE && part)
-      gamma_delta_terms(vs + face_off(slot, 0, bxc.nc), g, gx, gy, gz, bxc, (double)b[g], (double)zo,
-                        cell_k2h3<VAR>(bxc, g), p_zv, p_azz);
-  }
-  if (FINE && part) {
-    p_zv = block_sum(p_zv, red);
-    p_azz = block_sum(p_azz, red);
-    if (threadIdx.x == 0) {
-      part[((int64_t)slot * nb + t) * 2 + 0] = p_zv;
-      part[((int64_t)slot * nb + t) * 2 + 1] = p_azz;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// multigrid level kernels, 2.5-D variant: a block owns a TX x TY column tile
-// (one column per thread) and marches through ZC planes in z, keeping the
-// planes a stencil step needs in LDS rings.  The next plane's global loads are
-// issued into registers before the current plane is processed.  Same
-// arithmetic as the 3-D tile kernels above, element for element.
-
-template <int TX, int TY, int H>
-struct Plane {
-  static constexpr int W = TX + 2 * H, HH = TY + 2 * H, A = W * HH, R = (A + kBlock - 1) / kBlock;
-};
-
-template <typename TM, typename TB, int TX, int TY, int ZC, bool FINE>
-__global__ __launch_bounds__(kBlock) void k_mg_down_zs(const TB* __restrict__ b0, const TB* __restrict__ b1,
-                                                       TM* __restrict__ rH, Level L, int nb,
-                                                       const Scalars* __restrict__ sc) {
-  static_assert(TX * TY == kBlock && TX <= 32 && (TX % 2) == 0 && (TY % 2) == 0 && (ZC % 2) == 0, "tile");
-  using PB = Plane<TX, TY, 2>;
-  using PX = Plane<TX, TY, 1>;
-  __shared__ TM sb[3][PB::A];
-  __shared__ TM sx[3][PX::A];
-  const int m = L.m;
-  const int64_t m2 = (int64_t)m * m;
-  const int tpx = (m + TX - 1) / TX, tpy = (m + TY - 1) / TY;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int slot = lb / nb, t = lb - slot * nb;
-  const TB* b = b0;
-  if (sc) {
-    if (sc[slot].state != ST_ACTIVE) return;
-    if (FINE && (sc[slot].it & 1)) b = b1;
-  }
-  b += (int64_t)slot * L.nc;
-  const int x0 = (t % tpx) * TX, y0 = ((t / tpx) % tpy) * TY, z0 = (t / (tpx * tpy)) * ZC;
-  const int z1 = min(z0 + ZC, m);
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int gx = x0 + tx, gy = y0 + ty;
-  const bool own = gx < m && gy < m;
-  const Diag<TM> D(L.k2, L.a);
-  const TM a = D.a, cA = (TM)L.cA, cB = (TM)L.cB;
-
-  int boff[PB::R], bnn[PB::R];
-  bool bok[PB::R];
-#pragma unroll
-  for (int k = 0; k < PB::R; ++k) {
-    const int p = threadIdx.x + k * kBlock;
-    const int hx = x0 + p % PB::W - 2, hy = y0 + p / PB::W - 2;
-    bok[k] = p < PB::A && (unsigned)hx < (unsigned)m && (unsigned)hy < (unsigned)m;
-    boff[k] = bok[k] ? hx + m * hy : 0;
-    bnn[k] = (hx > 0) + (hx < m - 1) + (hy > 0) + (hy < m - 1);
-  }
-  TB pf[PB::R];
-  auto fetch = [&](int z) {
-    const bool zin = (unsigned)z < (unsigned)m;
-#pragma unroll
-    for (int k = 0; k < PB::R; ++k) pf[k] = (bok[k] && zin) ? b[boff[k] + m2 * z] : (TB)0;
-  };
-  const int zb = z0 - 2;
-  fetch(zb);
-  TM acc = 0;
-  const int nnxy = (gx > 0) + (gx < m - 1) + (gy > 0) + (gy < m - 1);
-  const int mH = m >> 1;
-  TM* r_out = rH + (int64_t)slot * mH * mH * mH;
-  for (int s = zb; s <= z1 + 1; ++s) {
-    {
-      TM* bs = sb[(s - zb) % 3];
-      const int zn = (s > 0) + (s < m - 1);
-#pragma unroll
-      for (int k = 0; k < PB::R; ++k) {
-        const int p = threadIdx.x + k * kBlock;
-        if (p < PB::A) bs[p] = (TM)pf[k] * D.inv(bnn[k] + zn);
-      }
-    }
-    if (s + 1 <= z1 + 1) fetch(s + 1);
-    __syncthreads();
-    const int zx = s - 1;
-    if (zx >= z0 - 1) {
-      TM* xs = sx[(zx - (z0 - 1)) % 3];
-      const TM* bm = sb[(zx - 1 - zb) % 3];
-      const TM* bc = sb[(zx - zb) % 3];
-      const TM* bp = sb[(zx + 1 - zb) % 3];
-      const bool zin = (unsigned)zx < (unsigned)m;
-      const int zn = (zx > 0) + (zx < m - 1);
-#pragma unroll
-      for (int k = 0; k < PX::R; ++k) {
-        const int p = threadIdx.x + k * kBlock;
-        if (p < PX::A) {
-          const int lx = p % PX::W, ly = p / PX::W;
-          const int hx = x0 + lx - 1, hy = y0 + ly - 1;
-          TM v = 0;
-          if (zin && (unsigned)hx < (unsigned)m && (unsigned)hy < (unsigned)m) {
-            const int q = (lx + 1) + PB::W * (ly + 1);
-            const TM sum = bc[q - 1] + bc[q + 1] + bc[q - PB::W] + bc[q + PB::W] + bm[q] + bp[q];
-            const int nn = (hx > 0) + (hx < m - 1) + (hy > 0) + (hy < m - 1) + zn;
-            v = cA * bc[q] + cB * D.inv(nn) * sum;
-          }
-          xs[p] = v;
-        }
-      }
-    }
-    __syncthreads();
-    const int zr = s - 2;
-    if (zr >= z0 && zr < z1) {
-      TM r = 0;
-      if (own) {
-        const int q = (tx + 2) + PB::W * (ty + 2);
-        const int u = (tx + 1) + PX::W * (ty + 1);
-        const TM* xc = sx[(zr - (z0 - 1)) % 3];
-        const TM* xm = sx[(zr - 1 - (z0 - 1)) % 3];
-        const TM* xp = sx[(zr + 1 - (z0 - 1)) % 3];
-        const TM d = D.d(nnxy + (zr > 0) + (zr < m - 1));
-        const TM sum = xc[u - 1] + xc[u + 1] + xc[u - PX::W] + xc[u + PX::W] + xm[u] + xp[u];
-        r = d * (sb[(zr - zb) % 3][q] - xc[u]) + a * sum;
-      }
-      acc += r;
-      if (zr & 1) {
-        TM v = acc + __shfl_xor(acc, 1, 64);
-        v += __shfl_xor(v, TX, 64);
-        if (own && !(tx & 1) && !(ty & 1))
-          r_out[(gx >> 1) + (int64_t)mH * ((gy >> 1) + (int64_t)mH * (zr >> 1))] = v;
-        acc = 0;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-template <typename TM, typename TB, typename TO, int TX, int TY, int ZC, bool FINE, bool VAR = false>
-__global__ __launch_bounds__(kBlock, 4) void k_mg_up_zs(const TB* __restrict__ b0, const TB* __restrict__ b1,
-                                                     const TM* __restrict__ eH, TO* __restrict__ o0,
-                                                     TO* __restrict__ o1, Level L, int nb,
-                                                     const Scalars* __restrict__ sc,
-                                                     const double* __restrict__ vs0,
-                                                     const double* __restrict__ vs1,
-                                                     double* __restrict__ part, Box bxc) {
-  static_assert(TX * TY == kBlock && (TX % 2) == 0 && (TY % 2) == 0 && (ZC % 2) == 0, "tile");
-  using PB = Plane<TX, TY, 3>;
-  using PX = Plane<TX, TY, 2>;
-  using PY = Plane<TX, TY, 1>;
-  __shared__ TM sb[4][PB::A];
-  __shared__ TM sx[4][PX::A];
-  __shared__ TM sy[3][PY::A];
-  __shared__ double red[kBlock / 64];
-  // fine level: the x- and y-face planes of the output plane (radius 3 along the line)
-  constexpr int FXW = TX + 6, FXA = FINE ? FXW * TY : 1, FYA = FINE ? TX * (TY + 6) : 1;
-  constexpr int FXR = (FXA + kBlock - 1) / kBlock, FYR = (FYA + kBlock - 1) / kBlock;
-  __shared__ double fxp[FXA];
-  __shared__ double fyp[FYA];
-  const int m = L.m;
-  const int64_t m2 = (int64_t)m * m;
-  const int tpx = (m + TX - 1) / TX, tpy = (m + TY - 1) / TY;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int slot = lb / nb, t = lb - slot * nb;
-  const TB* b = b0;
-  TO* o = o0;
-  const double* vs = vs0;
-  if (sc) {
-    if (sc[slot].state != ST_ACTIVE) return;
-    if (FINE && (sc[slot].it & 1)) { b = b1; o = o1; vs = vs1; }
-  }
-  b += (int64_t)slot * L.nc;
-  o += (int64_t)slot * L.nc;
-  const int mH = m >> 1;
-  const int64_t mH2 = (int64_t)mH * mH;
-  const TM* e = eH + (int64_t)slot * mH2 * mH;
-  const int x0 = (t % tpx) * TX, y0 = ((t / tpx) % tpy) * TY, z0 = (t / (tpx * tpy)) * ZC;
-  const int z1 = min(z0 + ZC, m);
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int gx = x0 + tx, gy = y0 + ty;
-  const bool own = gx < m && gy < m;
-  const Diag<TM> D(L.k2, L.a);
-  const TM a = D.a, cA = (TM)L.cA, cB = (TM)L.cB;
-  const TM c0 = (TM)L.c0, c1 = (TM)L.c1, c2 = (TM)L.c2;
-
-  int boff[PB::R], bnn[PB::R];
-  bool bok[PB::R];
-#pragma unroll
-  for (int k = 0; k < PB::R; ++k) {
-    const int p = threadIdx.x + k * kBlock;
-    const int hx = x0 + p % PB::W - 3, hy = y0 + p / PB::W - 3;
-    bok[k] = p < PB::A && (unsigned)hx < (unsigned)m && (unsigned)hy < (unsigned)m;
-    boff[k] = bok[k] ? hx + m * hy : 0;
-    bnn[k] = (hx > 0) + (hx < m - 1) + (hy > 0) + (hy < m - 1);
-  }
-  int eoff[PX::R];
-  bool eok[PX::R];
-#pragma unroll
-  for (int k = 0; k < PX::R; ++k) {
-    const int p = threadIdx.x + k * kBlock;
-    const int hx = x0 + p % PX::W - 2, hy = y0 + p / PX::W - 2;
-    eok[k] = p < PX::A && (unsigned)hx < (unsigned)m && (unsigned)hy < (unsigned)m;
-    eoff[k] = eok[k] ? (hx >> 1) + mH * (hy >> 1) : 0;
-  }
-  TB pf[PB::R];
-  TM pe[PX::R], pe_next[PX::R];
-  auto fetch_b = [&](int z) {
-    const bool zin = (unsigned)z < (unsigned)m;
-#pragma unroll
-    for (int k = 0; k < PB::R; ++k) pf[k] = (bok[k] && zin) ? b[boff[k] + m2 * z] : (TB)0;
-  };
-  auto fetch_e = [&](TM* dst, int z) {
-    const bool zin = (unsigned)z < (unsigned)m;
-#pragma unroll
-    for (int k = 0; k < PX::R; ++k) dst[k] = (eok[k] && zin) ? e[eoff[k] + mH2 * (z >> 1)] : (TM)0;
-  };
-  // face values for the partial sums of the output plane (fine level only)
-  const double* vsl = vs + face_off(slot, 0, bxc.nc);
-  const bool parts = FINE && part != nullptr;
-  double pfx[FXR], pfy[FYR];
-  double wzl[7] = {0, 0, 0, 0, 0, 0, 0}, wz_next = 0.0;
-  auto fetch_faces = [&](int z) {
-    if (!parts) return;
-    const bool zin = (unsigned)z < (unsigned)m;
-#pragma unroll
-    for (int k = 0; k < FXR; ++k) {
-      const int p = threadIdx.x + k * kBlock;
-      const int hx = x0 + p % FXW - 3, hy = y0 + p / FXW;
-      pfx[k] = (p < FXA && zin && hx >= 1 && hx <= m - 1 && hy < m) ? vsl[hx + (int64_t)m * hy + m2 * z] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < FYR; ++k) {
-      const int p = threadIdx.x + k * kBlock;
-      const int hx = x0 + p % TX, hy = y0 + p / TX - 3;
-      pfy[k] = (p < FYA && zin && hx < m && hy >= 1 && hy <= m - 1)
-                   ? vsl[bxc.nc + hx + (int64_t)m * hy + m2 * z] : 0.0;
-    }
-  };
-  auto fetch_wz = [&](int z) {
-    wz_next = (parts && own && z >= 1 && z <= m - 1) ? vsl[2 * bxc.nc + gx + (int64_t)m * gy + m2 * z] : 0.0;
-  };
-  const int zb = z0 - 3;
-  const int nnxy = (gx > 0) + (gx < m - 1) + (gy > 0) + (gy < m - 1);
-  double p_zv = 0.0, p_azz = 0.0;
-  fetch_b(zb);
-  fetch_faces(zb - 3);
-  fetch_wz(zb);
-#pragma unroll
-  for (int k = 0; k < PX::R; ++k) pe[k] = 0;
-  for (int s = zb; s <= z1 + 2; ++s) {
-    {
-      TM* bs = sb[(s - zb) & 3];
-      const int zn = (s > 0) + (s < m - 1);
-#pragma unroll
-      for (int k = 0; k < PB::R; ++k) {
-        const int p = threadIdx.x + k * kBlock;
-        if (p < PB::A) bs[p] = (TM)pf[k] * D.inv(bnn[k] + zn);
-      }
-    }
-    if (parts) {
-      // face planes of the output plane s-3 into LDS; z-faces slide through registers
-#pragma unroll
-      for (int k = 0; k < FXR; ++k) {
-        const int p = threadIdx.x + k * kBlock;
-        if (p < FXA) fxp[p] = pfx[k];
-      }
-#pragma unroll
-      for (int k = 0; k < FYR; ++k) {
-        const int p = threadIdx.x + k * kBlock;
-        if (p < FYA) fyp[p] = pfy[k];
-      }
-#pragma unroll
-      for (int k = 0; k < 6; ++k) wzl[k] = wzl[k + 1];
-      wzl[6] = wz_next;
-      fetch_faces(s - 2);
-      fetch_wz(s + 1);
-    }
-    if (s + 1 <= z1 + 2) fetch_b(s + 1);
-    fetch_e(pe_next, s);        // corrections of plane s (used at the next step)
-    __syncthreads();
-    const int zx = s - 1;
-    if (zx >= z0 - 2) {
-      TM* xs = sx[(zx - (z0 - 2)) & 3];
-      const TM* bm = sb[(zx - 1 - zb) & 3];
-      const TM* bc = sb[(zx - zb) & 3];
-      const TM* bp = sb[(zx + 1 - zb) & 3];
-      const bool zin = (unsigned)zx < (unsigned)m;
-      const int zn = (zx > 0) + (zx < m - 1);
-#pragma unroll
-      for (int k = 0; k < PX::R; ++k) {
-        const int p = threadIdx.x + k * kBlock;
-        if (p < PX::A) {
-          const int lx = p % PX::W, ly = p / PX::W;
-          const int hx = x0 + lx - 2, hy = y0 + ly - 2;
-          TM v = 0;
-          if (zin && (unsigned)hx < (unsigned)m && (unsigned)hy < (unsigned)m) {
-            const int q = (lx + 1) + PB::W * (ly + 1);
-            const TM sum = bc[q - 1] + bc[q + 1] + bc[q - PB::W] + bc[q + PB::W] + bm[q] + bp[q];
-            const int nn = (hx > 0) + (hx < m - 1) + (hy > 0) + (hy < m - 1) + zn;
-            v = cA * bc[q] + cB * D.inv(nn) * sum + pe[k];
-          }
-          xs[p] = v;
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < PX::R; ++k) pe[k] = pe_next[k];
-    __syncthreads();
-    const int zy = s - 2;
-    if (zy >= z0 - 1) {
-      TM* ys = sy[(zy - (z0 - 1)) % 3];
-      const TM* xm = sx[(zy - 1 - (z0 - 2)) & 3];
-      const TM* xc = sx[(zy - (z0 - 2)) & 3];
-      const TM* xp = sx[(zy + 1 - (z0 - 2)) & 3];
-      const TM* bc = sb[(zy - zb) & 3];
-      const bool zin = (unsigned)zy < (unsigned)m;
-      const int zn = (zy > 0) + (zy < m - 1);
-#pragma unroll
-      for (int k = 0; k < PY::R; ++k) {
-        const int p = threadIdx.x + k * kBlock;
-        if (p < PY::A) {
-          const int lx = p % PY::W, ly = p / PY::W;
-          const int hx = x0 + lx - 1, hy = y0 + ly - 1;
-          TM v = 0;
-          if (zin && (unsigned)hx < (unsigned)m && (unsigned)hy < (unsigned)m) {
-            const int q = (lx + 2) + PB::W * (ly + 2);
-            const int u = (lx + 1) + PX::W * (ly + 1);
-            const TM sum = xc[u - 1] + xc[u + 1] + xc[u - PX::W] + xc[u + PX::W] + xm[u] + xp[u];
-            const int nn = (hx > 0) + (hx < m - 1) + (hy > 0) + (hy < m - 1) + zn;
-            const TM rr = D.d(nn) * (bc[q] - xc[u]) + a * sum;
-            v = c0 * D.inv(nn) * rr;
-          }
-          ys[p] = v;
-        }
-      }
-    }
-    __syncthreads();
-    const int zo = s - 3;
-    if (zo >= z0 && zo < z1 && own) {
-      const int q = (tx + 3) + PB::W * (ty + 3);
-      const int u = (tx + 2) + PX::W * (ty + 2);
-      const int w = (tx + 1) + PY::W * (ty + 1);
-      const TM* xm = sx[(zo - 1 - (z0 - 2)) & 3];
-      const TM* xc = sx[(zo - (z0 - 2)) & 3];
-      const TM* xp = sx[(zo + 1 - (z0 - 2)) & 3];
-      const TM* ym = sy[(zo - 1 - (z0 - 1)) % 3];
-      const TM* yc = sy[(zo - (z0 - 1)) % 3];
-      const TM* yp = sy[(zo + 1 - (z0 - 1)) % 3];
-      const int nn = nnxy + (zo > 0) + (zo < m - 1);
-      const TM d = D.d(nn);
-      const TM sxn = xc[u - 1] + xc[u + 1] + xc[u - PX::W] + xc[u + PX::W] + xm[u] + xp[u];
-      const TM syn = yc[w - 1] + yc[w + 1] + yc[w - PY::W] + yc[w + PY::W] + ym[w] + yp[w];
-      const TM rr = d * (sb[(zo - zb) & 3][q] - xc[u]) + a * sxn;
-      const TM t2 = rr - (d * yc[w] - a * syn);
-      const TM out = xc[u] + c1 * yc[w] + c2 * D.inv(nn) * t2;
-      const int64_t g = gx + (int64_t)m * gy + m2 * zo;
-      const TO zo_v = (TO)out;
-      o[g] = zo_v;
-      if (parts) {
-        double wx[7], wy[7];
-#pragma unroll
-        for (int k = 0; k < 7; ++k) {
-          wx[k] = fxp[tx + k + FXW * ty];
-          wy[k] = fyp[tx + TX * (ty + k)];
-        }
-        gamma_delta_lines(wx, wy, wzl, gx, gy, zo, bxc, (double)b[g], (double)zo_v, cell_k2h3<VAR>(bxc, g), p_zv, p_azz);
-      }
-    }
-    __syncthreads();
-  }
-  if (FINE && part) {
-    p_zv = block_sum(p_zv, red);
-    p_azz = block_sum(p_azz, red);
-    if (threadIdx.x == 0) {
-      part[((int64_t)slot * nb + t) * 2 + 0] = p_zv;
-      part[((int64_t)slot * nb + t) * 2 + 1] = p_azz;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// multigrid: all levels from `top` down to 1^3 and back, in LDS, one block per
-// slot.  Each level keeps four arrays (b, x, y, t) of m^3 values.
-
-template <typename TM>
-__device__ __forceinline__ TM nsum(const TM* v, int x, int y, int z, int m, int c) {
-  TM s = 0;
-  if (x > 0) s += v[c - 1];
-  if (x < m - 1) s += v[c + 1];
-  if (y > 0) s += v[c - m];
-  if (y < m - 1) s += v[c + m];
-  if (z > 0) s += v[c - m * m];
-  if (z < m - 1) s += v[c + m * m];
-  return s;
-}
-
-// Threads of the persistent coarse-level kernel (one block per sample; the
-// 16^3 level is its largest, so 1024 threads leave 4 cells per thread).
-constexpr int kCoarseBlock = 1024;
-
-template <typename TM>
-__global__ __launch_bounds__(kCoarseBlock) void k_mg_coarse(const TM* __restrict__ btop, TM* __restrict__ etop,
-                                                      CoarseParams P, const Scalars* __restrict__ sc) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  TM* sm = reinterpret_cast<TM*>(smem_raw);
-  const int slot = blockIdx.x;
-  if (sc && sc[slot].state != ST_ACTIVE) return;
-  const int m0 = P.lv[0].m;
-  const int64_t nc0 = P.lv[0].nc;
-  {
-    TM* b = sm + P.off[0];
-    for (int c = threadIdx.x; c < nc0; c += kCoarseBlock) b[c] = btop[(int64_t)slot * nc0 + c];
-  }
-  __syncthreads();
-  for (int l = 0; l < P.nl - 1; ++l) {
-    const Level& L = P.lv[l];
-    const int m = L.m;
-    const int nc = (int)L.nc;
-    TM* b = sm + P.off[l];
-    TM* x = b + nc;
-    TM* y = x + nc;
-    TM* tt = y + nc;
-    const TM k2 = (TM)L.k2, a = (TM)L.a, c0 = (TM)L.c0, c1 = (TM)L.c1, c2 = (TM)L.c2;
-    for (int c = threadIdx.x; c < nc; c += kCoarseBlock) {
-      const int i = c % m, j = (c / m) % m, k = c / (m * m);
-      y[c] = c0 * b[c] / (k2 + a * (TM)nnbr(i, j, k, m));
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < nc; c += kCoarseBlock) {
-      const int i = c % m, j = (c / m) % m, k = c / (m * m);
-      const TM d = k2 + a * (TM)nnbr(i, j, k, m);
-      const TM Ay = d * y[c] - a * nsum(y, i, j, k, m, c);
-      x[c] = c1 * y[c] + (c2 / d) * (b[c] - Ay);
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < nc; c += kCoarseBlock) {
-      const int i = c % m, j = (c / m) % m, k = c / (m * m);
-      const TM d = k2 + a * (TM)nnbr(i, j, k, m);
-      tt[c] = b[c] - (d * x[c] - a * nsum(x, i, j, k, m, c));
-    }
-    __syncthreads();
-    const int mh = m >> 1;
-    TM* bn = sm + P.off[l + 1];
-    for (int C = threadIdx.x; C < mh * mh * mh; C += kCoarseBlock) {
-      const int I = C % mh, J = (C / mh) % mh, K = C / (mh * mh);
-      TM acc = 0;
-#pragma unroll
-      for (int ch = 0; ch < 8; ++ch) {
-        const int i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
-        acc += tt[i + m * (j + m * k)];
-      }
-      bn[C] = acc;
-    }
-    __syncthreads();
-  }
-  {
-    const Level& L = P.lv[P.nl - 1];
-    const int m = L.m;
-    const int nc = (int)L.nc;
-    TM* b = sm + P.off[P.nl - 1];
-    TM* x = b + nc;
-    // coarsest level: a single cell, S~ = kappa^2 H^3 (no neighbours): exact
-    for (int c = threadIdx.x; c < nc; c += kCoarseBlock) {
-      const int i = c % m, j = (c / m) % m, k = c / (m * m);
-      x[c] = b[c] / ((TM)L.k2 + (TM)L.a * (TM)nnbr(i, j, k, m));
-    }
-    __syncthreads();
-  }
-  for (int l = P.nl - 2; l >= 0; --l) {
-    const Level& L = P.lv[l];
-    const int m = L.m;
-    const int nc = (int)L.nc;
-    const int mh = m >> 1;
-    TM* b = sm + P.off[l];
-    TM* x = b + nc;
-    TM* y = x + nc;
-    TM* tt = y + nc;
-    const TM* xn = sm + P.off[l + 1] + (int)P.lv[l + 1].nc;
-    const TM k2 = (TM)L.k2, a = (TM)L.a, c0 = (TM)L.c0, c1 = (TM)L.c1, c2 = (TM)L.c2;
-    for (int c = threadIdx.x; c < nc; c += kCoarseBlock) {
-      const int i = c % m, j = (c / m) % m, k = c / (m * m);
-      x[c] += xn[(i >> 1) + mh * ((j >> 1) + mh * (k >> 1))];
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < nc; c += kCoarseBlock) {
-      const int i = c % m, j = (c / m) % m, k = c / (m * m);
-      const TM d = k2 + a * (TM)nnbr(i, j, k, m);
-      const TM r = b[c] - (d * x[c] - a * nsum(x, i, j, k, m, c));
-      tt[c] = r;
-      y[c] = c0 * r / d;
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < nc; c += kCoarseBlock) {
-      const int i = c % m, j = (c / m) % m, k = c / (m * m);
-      const TM d = k2 + a * (TM)nnbr(i, j, k, m);
-      const TM t2 = tt[c] - (d * y[c] - a * nsum(y, i, j, k, m, c));
-      x[c] += c1 * y[c] + (c2 / d) * t2;
-    }
-    __syncthreads();
-  }
-  {
-    const TM* x = sm + P.off[0] + nc0;
-    for (int c = threadIdx.x; c < nc0; c += kCoarseBlock) etop[(int64_t)slot * nc0 + c] = x[c];
-  }
-  (void)m0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1044,302 +146,6 @@ __global__ __launch_bounds__(kBlock) void k_scalar(Fields F, int nb_up, int nb_p
   s.pit = j;
   s.it = j + 1;
   *S = s;
-}
-
-// ---------------------------------------------------------------------------
-// operator pass of iteration j:
-//   v_{j+1} = A z_j - a_v v_j - b_v v_{j-1},  z_j = (P_sigma^-1 v_sigma, zhat_u) / gamma_j
-// and the delayed direction/solution update of step j-1.  One thread per
-// cell: the cell value and the three low faces of the cell.
-//   (M z)_face = (M P_sigma^-1 v)_f / gamma              (line_terms)
-//   (B^T z_u)_face = h^2 (zhat[c - e_d] - zhat[c]) / gamma
-//   (A z)_cell = (h^2 q sum_d (z_hi - z_lo) / q - kappa^2 h^3 zhat) / gamma
-
-// Face window along one grid line extended by odd reflection about the
-// boundary faces 0 and n (v_{-g} = -v_g, v_n = 0): w[k + 3] = v_{idx + k},
-// k = -R..R, zero outside the radius.  Every load is issued unconditionally
-// from an address on the line; the reflection makes the interior stencils of
-// line_terms_ext exact next to the boundary as well.
-template <int R>
-__device__ __forceinline__ void line_load_ext(const double* __restrict__ v, int64_t c, int64_t stride, int idx,
-                                              int n, double* w) {
-#pragma unroll
-  for (int k = -3; k <= 3; ++k) {
-    if (k < -R || k > R) {
-      w[k + 3] = 0.0;
-      continue;
-    }
-    const int g = idx + k;
-    const bool neg = g < 0 || g > n;
-    const int src = g < 0 ? -g : (g > n ? 2 * n - g : g);
-    const double x = v[c + (int64_t)(min(src, n - 1) - idx) * stride];
-    // a factor, not a select: a select lets the compiler move the load into a
-    // branch and wait for it there
-    w[k + 3] = x * (src == n ? 0.0 : (neg ? -1.0 : 1.0));
-  }
-}
-
-// line_terms on a reflected window (no boundary cases).
-__device__ __forceinline__ void line_terms_ext(const double* w, int poly, double& mz, double& zf, double& zh) {
-  if (poly) {
-    const double a = w[2] + w[4];
-    zf = 1.125 * w[3] - 0.25 * a + 0.0625 * (w[1] + w[5]);
-    zh = 1.125 * w[4] - 0.25 * (w[3] + w[5]) + 0.0625 * (w[2] + w[6]);
-    mz = w[3] + 0.015625 * ((w[0] + w[6]) + 3.0 * a);
-  } else {
-    mz = w[3] + 0.25 * (w[2] + w[4]);
-    zf = w[3];
-    zh = w[4];
-  }
-}
-
-// UNI: every wave lies in one grid row (n >= 64), so the y and z line
-// positions, and with them the y- and z-window offsets, are wave-uniform.
-// POLY: face block of the preconditioner (0 diag(M)^-1, 1 Neumann series), a
-// template parameter so that no window load sits behind a branch on it.
-// VAR: cell-wise kappa (the reaction term kappa_c^2 h^3 of the cell row).
-template <typename TZ, bool UNI, int POLY, bool VAR>
-__global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int slot = lb / nb, blk = lb - slot * nb;
-  const Scalars* S = F.sc + slot;
-  const int state = S->state;
-  if (state != ST_ACTIVE && state != ST_FINISH) return;
-  const int j = S->pit;
-  const int p = j & 1, pq = p ^ 1;
-  const int64_t nc = bx.nc;
-  const int n = bx.n;
-  const int64_t n2 = bx.n2;
-  const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
-  if (c >= nc) return;
-  const int i = (int)(c % n);
-  int jj = (int)((c / n) % n), k = (int)(c / n2);
-  if constexpr (UNI) {
-    jj = __builtin_amdgcn_readfirstlane(jj);
-    k = __builtin_amdgcn_readfirstlane(k);
-  }
-  const int64_t co = cell_off(slot, nc);
-  const bool active = state == ST_ACTIVE;
-  const bool has_prev = j > 1;
-  const int wm = S->wmode;
-  // x is written on even iterations and on the finishing pass; an odd
-  // iteration leaves its term to the next pass (coefficient xpend of W_{j-1})
-  const bool upd_x = wm >= 1 && ((j & 1) == 0 || state == ST_FINISH);
-  const int idx[3] = {i, jj, k};
-  const int64_t str[3] = {1, n, n2};
-  // scalars before any store (after a store they could no longer be scalar loads)
-  const double zs = S->zs, av = S->a_v, bv = S->b_v;
-  const double sww = S->ww, swwp = S->ww_prev, sxw = S->xw, sxp = S->xpend;
-  const bool acc = S->flags & FL_ACCUM;   // refinement pass: x holds the previous iterate
-
-  // Direction and solution updates (unnormalised directions, see Scalars):
-  //   W_{j+1} = zs zhat_j + ww W_j + ww_prev W_{j-1}      (W_j in w[pq], W_{j-1} in w[p])
-  //   x += xpend W_{j-1} + xw W_j                          (even passes, the finishing pass)
-  // The W store is unconditional (a pass without update writes back the old
-  // value) so that the loads it needs stay ahead of the other stores.
-  auto x_update = [&](double wj, double wjm1) {
-    if (upd_x) {
-      const double inc = sxp * wjm1 + sxw * wj;
-      F.x[co + c] = (j == 2 && !acc) ? inc : F.x[co + c] + inc;
-    }
-  };
-  if (!active) {   // the finishing pass only applies the last solution update
-    x_update(F.w[pq][co + c], wm >= 2 ? F.w[p][co + c] : 0.0);
-    return;
-  }
-  // All loads first, unconditionally (the addresses are valid in every state;
-  // values that a state does not need are discarded).  The stores go through
-  // pointers that may alias the loads, so a load after a store, or inside a
-  // branch the compiler may sink below the stores, would cost the wave another
-  // memory round trip.
-  const TZ* z = reinterpret_cast<const TZ*>(F.z[p]) + co;
-  double w[3][7], vo[3], zlo[3];
-  const double zc = (double)z[c];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    // radius 3 in either face-block mode (a branch here would split the
-    // loads into groups that each wait for their own data)
-    line_load_ext<3>(F.vs[p] + face_off(slot, d, nc), c, str[d], idx[d], n, w[d]);
-    zlo[d] = (double)z[idx[d] > 0 ? c - str[d] : c];
-    vo[d] = F.vs[pq][face_off(slot, d, nc) + c];
-  }
-  const double vuc = F.vu[p][co + c], vuo = F.vu[pq][co + c];
-  const double wj = F.w[pq][co + c], wjm1 = F.w[p][co + c];
-  // VAR: cell-wise kappa (shared by the slots), read with the other loads
-  const double kc = VAR ? bx.kap[c] : 0.0;
-
-  double dv = 0.0, nf[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    double mz, zf, zh;
-    line_terms_ext(w[d], POLY, mz, zf, zh);
-    dv += zh - zf;
-    const double a = zs * (mz + bx.h2 * (zlo[d] - zc));
-    const double nv = a - av * w[d][3];
-    nf[d] = idx[d] > 0 ? (has_prev ? nv - bv * vo[d] : nv) : 0.0;
-  }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) F.vs[pq][face_off(slot, d, nc) + c] = nf[d];
-  const double k2 = VAR ? (kc * kc) * bx.h3 : bx.k2h3;
-  const double Au = zs * (bx.h2q * dv - k2 * zc);
-  const double nu = Au - av * vuc;
-  F.vu[pq][co + c] = has_prev ? nu - bv * vuo : nu;
-  double wn = zs * zc;
-  if (wm >= 1) wn += sww * wj;
-  if (wm >= 2) wn += swwp * wjm1;
-  F.w[p][co + c] = wm >= 0 ? wn : wjm1;
-  if (wm >= 1) x_update(wj, wm >= 2 ? wjm1 : 0.0);
-}
-
-// Column form of the operator pass for n a multiple of 64.  A block owns
-// 64 x 4 cell columns (one grid row per wave) and walks ZC planes up z.  The
-// z-window of the z faces slides in registers (one new plane per step), the z
-// neighbour of zhat is the previous step's value, and each step stages the x
-// faces of its 4 rows (with a 3-face halo along x) and the y faces of rows
-// -3 .. +6 in LDS, from which the x and y windows are read.  Same arithmetic,
-// in the same order, as k_operator.
-template <typename TZ, int POLY, bool VAR, int ZC>
-__global__ __launch_bounds__(kBlock) void k_operator_col(Fields F, Box bx, int nb) {
-  constexpr int XW = 64 + 6, AXF = XW * 4, RXF = (AXF + kBlock - 1) / kBlock;   // x faces, halo 3 in x
-  constexpr int AYF = 64 * (4 + 6), RYF = (AYF + kBlock - 1) / kBlock;           // y faces, halo 3 in y
-  __shared__ double sxf[2][AXF];
-  __shared__ double syf[2][AYF];
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int slot = lb / nb, t = lb - slot * nb;
-  const Scalars* S = F.sc + slot;
-  const int state = S->state;
-  if (state != ST_ACTIVE && state != ST_FINISH) return;
-  const int j = S->pit;
-  const int p = j & 1, pq = p ^ 1;
-  const int64_t nc = bx.nc;
-  const int n = bx.n;
-  const int64_t n2 = bx.n2;
-  const int tpx = n >> 6, tpy = n >> 2;
-  const int x0 = (t % tpx) << 6, y0 = ((t / tpx) % tpy) << 2, z0 = (t / (tpx * tpy)) * ZC;
-  const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int i = x0 + lane;
-  const int jj = __builtin_amdgcn_readfirstlane(y0 + wv);
-  const int64_t col = i + (int64_t)n * jj;
-  const int64_t co = cell_off(slot, nc);
-  const bool active = state == ST_ACTIVE;
-  const bool has_prev = j > 1;
-  const int wm = S->wmode;
-  const bool upd_x = wm >= 1 && ((j & 1) == 0 || state == ST_FINISH);
-  const double zs = S->zs, av = S->a_v, bv = S->b_v;
-  const double sww = S->ww, swwp = S->ww_prev, sxw = S->xw, sxp = S->xpend;
-  const bool acc = S->flags & FL_ACCUM;   // refinement pass: x holds the previous iterate
-  auto x_update = [&](int64_t c, double wj, double wjm1) {
-    if (upd_x) {
-      const double inc = sxp * wjm1 + sxw * wj;
-      F.x[co + c] = (j == 2 && !acc) ? inc : F.x[co + c] + inc;
-    }
-  };
-  if (!active) {
-    for (int kk = 0; kk < ZC; ++kk) {
-      const int64_t c = col + n2 * (z0 + kk);
-      x_update(c, F.w[pq][co + c], wm >= 2 ? F.w[p][co + c] : 0.0);
-    }
-    return;
-  }
-  // staged items: byte offset within a plane and the odd-reflection factor
-  uint32_t xo[RXF], yo[RYF];
-  double xf[RXF], yf[RYF];
-#pragma unroll
-  for (int r = 0; r < RXF; ++r) {
-    const int q = tid + r * kBlock;
-    const int gx = x0 + q % XW - 3, gy = y0 + q / XW;
-    const bool neg = gx < 0 || gx > n;
-    const int src = gx < 0 ? -gx : (gx > n ? 2 * n - gx : gx);
-    xo[r] = q < AXF ? (uint32_t)(min(src, n - 1) + n * gy) * 8u : 0u;
-    xf[r] = (q >= AXF || src == n) ? 0.0 : (neg ? -1.0 : 1.0);
-  }
-#pragma unroll
-  for (int r = 0; r < RYF; ++r) {
-    const int q = tid + r * kBlock;
-    const int gx = x0 + q % 64, gy = y0 + q / 64 - 3;
-    const bool neg = gy < 0 || gy > n;
-    const int src = gy < 0 ? -gy : (gy > n ? 2 * n - gy : gy);
-    yo[r] = q < AYF ? (uint32_t)(gx + n * min(src, n - 1)) * 8u : 0u;
-    yf[r] = (q >= AYF || src == n) ? 0.0 : (neg ? -1.0 : 1.0);
-  }
-  const TZ* z = reinterpret_cast<const TZ*>(F.z[p]) + co;
-  const double* vs0 = F.vs[p] + face_off(slot, 0, nc);
-  const double* vs1 = F.vs[p] + face_off(slot, 1, nc);
-  const double* vz = F.vs[p] + face_off(slot, 2, nc) + col;
-  // z face of plane g of this column, odd reflection about the boundary faces
-  // 0 and n (the plane index is block-uniform, so the reflection is scalar)
-  auto face_z = [&](int g) {
-    const bool neg = g < 0 || g > n;
-    const int src = g < 0 ? -g : (g > n ? 2 * n - g : g);
-    const double x = vz[n2 * min(src, n - 1)];
-    return x * (src == n ? 0.0 : (neg ? -1.0 : 1.0));
-  };
-  double wz[7];
-#pragma unroll
-  for (int q = 0; q < 6; ++q) wz[q] = face_z(z0 - 3 + q);
-  double zprev = (double)z[col + n2 * max(z0 - 1, 0)];
-  for (int kk = 0; kk < ZC; ++kk) {
-    const int k = z0 + kk;
-    const int64_t pk = n2 * k;
-    const int64_t c = col + pk;
-    const int b = kk & 1;
-    // stage this plane's x and y faces (the buffer written two steps ago has
-    // been read by everyone: the previous step's barrier lies between)
-    const double* px = vs0 + pk;
-    const double* py = vs1 + pk;
-#pragma unroll
-    for (int r = 0; r < RXF; ++r) {
-      const int q = tid + r * kBlock;
-      if ((r + 1) * kBlock <= AXF || q < AXF) sxf[b][q] = ld_off(px, xo[r]) * xf[r];
-    }
-#pragma unroll
-    for (int r = 0; r < RYF; ++r) {
-      const int q = tid + r * kBlock;
-      if ((r + 1) * kBlock <= AYF || q < AYF) syf[b][q] = ld_off(py, yo[r]) * yf[r];
-    }
-    wz[6] = face_z(k + 3);
-    double vo[3];
-    const double zc = (double)z[c];
-    const double zlo[3] = {(double)z[i > 0 ? c - 1 : c], (double)z[jj > 0 ? c - n : c], k > 0 ? zprev : zc};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) vo[d] = F.vs[pq][face_off(slot, d, nc) + c];
-    const double vuc = F.vu[p][co + c], vuo = F.vu[pq][co + c];
-    const double wj = F.w[pq][co + c], wjm1 = F.w[p][co + c];
-    const double kc = VAR ? bx.kap[c] : 0.0;
-    __syncthreads();
-    double w[2][7];
-#pragma unroll
-    for (int q = 0; q < 7; ++q) {
-      w[0][q] = sxf[b][lane + q + XW * wv];
-      w[1][q] = syf[b][lane + 64 * (wv + q)];
-    }
-    const int idx[3] = {i, jj, k};
-    double dv = 0.0, nf[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double* wd = d == 2 ? wz : w[d];
-      double mz, zf, zh;
-      line_terms_ext(wd, POLY, mz, zf, zh);
-      dv += zh - zf;
-      const double a = zs * (mz + bx.h2 * (zlo[d] - zc));
-      const double nv = a - av * wd[3];
-      nf[d] = idx[d] > 0 ? (has_prev ? nv - bv * vo[d] : nv) : 0.0;
-    }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) F.vs[pq][face_off(slot, d, nc) + c] = nf[d];
-    const double k2 = VAR ? (kc * kc) * bx.h3 : bx.k2h3;
-    const double Au = zs * (bx.h2q * dv - k2 * zc);
-    const double nu = Au - av * vuc;
-    F.vu[pq][co + c] = has_prev ? nu - bv * vuo : nu;
-    double wn = zs * zc;
-    if (wm >= 1) wn += sww * wj;
-    if (wm >= 2) wn += swwp * wjm1;
-    F.w[p][co + c] = wm >= 0 ? wn : wjm1;
-    if (wm >= 1) x_update(c, wj, wm >= 2 ? wjm1 : 0.0);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) wz[q] = wz[q + 1];
-    zprev = zc;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1633,7 +439,6 @@ __global__ __launch_bounds__(kBlock) void k_convert(const TS* __restrict__ s, TD
 
 }  // namespace spde
 
-#include "spde_vcycle.inc"
 #include "spde_rng.inc"
 #include "spde_transfer.inc"
 #include "spde_launch.inc"

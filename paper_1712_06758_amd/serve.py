@@ -48,6 +48,7 @@ class Part:
     slot: int = -1
     iters: int = 0
     result: object = None      # u_tet tensor (GPU engine) or None
+    done_event: object = None  # marks the end of the part's projection on its engine's stream
 
 
 @dataclass
@@ -207,13 +208,12 @@ class GpuEngine:
             _abi.check(L.spde_csr_apply(n_tet, nnz, C.c_void_p(rp.data_ptr()), C.c_void_p(ci.data_ptr()),
                                         C.c_void_p(cv.data_ptr()), self.n ** 3, 1, C.c_void_p(u.data_ptr()),
                                         C.c_void_p(ut.data_ptr()), C.c_void_p(od.data_ptr()), self._sp()))
+            part.done_event = torch.cuda.Event()
+            part.done_event.record(self.stream)
         del self.busy[part.slot]
         self.free.append(part.slot)
         part.result = ut
         return ut
-
-    def sync(self):
-        self.stream.synchronize()
 
 
 # ---------------------------------------------------------------------------
@@ -312,7 +312,11 @@ class Server:
                 part.result = None
             req.pending -= 1
             if req.pending == 0:
-                e.sync()
+                # the parts ran on different engines' streams: the request is
+                # done when the last projection of every part has finished
+                for p in req.parts:
+                    if p.done_event is not None:
+                        p.done_event.synchronize()
                 req.t_done = self.clock() - t0
                 self.in_flight -= req.footprint
                 self.done.append(req)

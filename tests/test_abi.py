@@ -74,11 +74,15 @@ def test_noise_entry_points_validate_before_launching(lib):
     assert L.spde_philox4x64(1, 2, 0, 0, 4, None, None) == -1
     assert L.spde_sample_seeded(None, 1, 1, 0, 0, None, None, None, None, None, None) == -1
     assert L.spde_slot_start_seeded(None, 0, 1, 0, 0, None) == -1
-    assert L.spde_sample_warm(None, 1, buf, buf, None, None, None, None, None, None) == -1
+    assert L.spde_sample_warm(None, 1, buf, buf, 512, None, None, None, None, None, None) == -1
     st, h = setup(lib, 16)
     assert st == 0
-    assert L.spde_sample_warm(h, 1, buf, None, None, None, None, None, None, None) == -1   # no coarse field
-    assert L.spde_sample_warm(h, 1, None, buf, None, None, None, None, None, None) == -1   # no noise
+    assert L.spde_sample_warm(h, 1, buf, None, 512, None, None, None, None, None, None) == -1   # no coarse field
+    assert L.spde_sample_warm(h, 1, None, buf, 512, None, None, None, None, None, None) == -1   # no noise
+    # the coarse field must hold batch (n/2)^3 values
+    assert L.spde_sample_warm(h, 1, buf, buf, 511, None, None, None, None, None, None) == -1
+    assert b"511" in L.spde_last_error()
+    assert L.spde_sample_warm(h, 2, buf, buf, 512, None, None, None, None, None, None) == -1
     lib.spde_destroy(h)
     assert L.spde_last_error()
 
