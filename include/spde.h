@@ -226,16 +226,28 @@ spde_status spde_restrict_noise(int n_fine, int batch, const double* xi_f_dev,
  *     the handle samples); NULL = the constant of spde_setup_box.  Values must
  *     be finite, kappa > 0 and g >= 0 (not checked: a non-finite value makes
  *     the samples fail with SPDE_EFAILED).
- *   kappa_ref: the constant kappa of the multigrid preconditioner S~ (the
- *     operator always uses the cell values).  Required (> 0) with a kappa
- *     field; sqrt(kappa_min kappa_max) keeps every kappa_c^2 / kappa_ref^2
- *     within [kappa_min / kappa_max, kappa_max / kappa_min].  0 without a
- *     kappa field keeps the setup kappa.
+ *   kappa_ref: the reaction coefficient of the multigrid preconditioner S~
+ *     (the operator always uses the cell values).
+ *     0 with a kappa field (the recommended form): the multigrid takes the
+ *       cell-wise kappa.  The finest level's reaction diagonal is
+ *       kappa_c^2 h^3; each coarser level's is the Galerkin one, the sum of the
+ *       8 children's (the coarse kappa^2 is the children's mean, eq.
+ *       ml-linsys).  The smoother's diagonal is the cell's, and its Chebyshev
+ *       interval comes from kappa_min.  The level diagonals are built, once, by
+ *       the next sampling, V-cycle or slot-reset call.  That call synchronises
+ *       its stream and returns SPDE_EINVAL if some kappa_c is not positive and
+ *       finite.
+ *     > 0: one constant kappa_ref in the whole hierarchy, e.g.
+ *       sqrt(kappa_min kappa_max).  This takes more iterations as the contrast
+ *       grows.
+ *     0 without a kappa field keeps the setup kappa.
+ * The preconditioner stays symmetric positive definite in both forms, so the
+ * solution does not depend on the choice; only the iteration count does.
  * Coupled coarse samples (eq. ml-linsys): the Galerkin coarse reaction block
  * has kappa_c^2 = mean of the 8 children's kappa^2; the coarse load equals the
  * restricted one when g is constant on each coarse cell.
  * Call between sampling calls (not while slots iterate).  Host-only: returns
- * SPDE_EINVAL for a bad kappa_ref. */
+ * SPDE_EINVAL for a negative or non-finite kappa_ref. */
 spde_status spde_set_coefficients(spde_handle h, const double* kappa_dev, const double* g_dev,
                                   double kappa_ref);
 
@@ -329,6 +341,19 @@ spde_status spde_csr_apply(int64_t n_rows, int64_t nnz, const int64_t* row_ptr_d
 spde_status spde_apply_operator(spde_handle h, int batch, const double* x_sigma_dev,
                                 const double* x_u_dev, double* y_sigma_dev,
                                 double* y_u_dev, void* stream);
+
+/* The production operator pass on a given direction:
+ *   y = A blkdiag(P_f diag(M), I) x,
+ * i.e. A applied to z = (P_f diag(M) x_sigma, x_u), where P_f is the handle's
+ * face block of the MINRES preconditioner (spde_set_face_preconditioner:
+ * diag(M)^-1, or the truncated Neumann series of M^-1 about its diagonal) and
+ * x_u enters in the multigrid precision (rounded to float32 in mixed
+ * precision), exactly as the solver's fused Lanczos pass forms A z.  Layouts
+ * and conditions as spde_apply_operator.  For checking the solver's own
+ * kernel instances against an explicit matrix. */
+spde_status spde_apply_operator_precond(spde_handle h, int batch, const double* x_sigma_dev,
+                                        const double* x_u_dev, double* y_sigma_dev, double* y_u_dev,
+                                        void* stream);
 
 /* z = V r: one V-cycle of the configured precision on the approximate Schur
  * complement (the u-block of the preconditioner).  r, z [batch][n^3].

@@ -88,6 +88,26 @@ def block_preconditioner(ops, kappa: float):
     return apply
 
 
+def face_block_series(ops):
+    """Face block of the GPU solver's default MINRES preconditioner, as a
+    sparse matrix: the Neumann series of M^-1 about its diagonal,
+
+        M^-1 = (D (I + D^-1 E))^-1 = sum_k (-D^-1 E)^k D^-1,  D = diag(M), E = M - D,
+
+    truncated after the second-order term:
+        P_f = D^-1 - D^-1 E D^-1 + D^-1 E D^-1 E D^-1.
+    (The paper's approximate Schur complement of eq. ldu and its Remark uses
+    the first term, diag(M)^-1, as the face block; either choice leaves the
+    solution unchanged.)"""
+    import scipy.sparse as sp
+    M = ops["M"].tocsr()
+    d = M.diagonal()
+    Dinv = sp.diags(1.0 / d)
+    E = (M - sp.diags(d)).tocsr()
+    T = Dinv @ E @ Dinv
+    return (Dinv - T + T @ E @ Dinv).tocsr()
+
+
 def solve(ops, kappa: float, F: np.ndarray, tol=1e-12, maxiter=10000):
     """Solve eq. linsys with block-preconditioned MINRES from x0 = 0.
 

@@ -280,9 +280,10 @@ class Box:
     def set_coefficients(self, kappa=None, g=None, kappa_ref: float | None = None):
         """Cell-wise kappa(x) and g(x) ([n^3] float64, cell order; host arrays are
         copied to the device, device tensors are used in place and must stay
-        alive).  kappa_ref: constant kappa of the multigrid preconditioner
-        (default for host arrays: sqrt(min kappa * max kappa); required for a
-        device kappa tensor).  set_coefficients() restores the constants."""
+        alive).  kappa_ref: None or 0 (default) puts the cell-wise kappa into
+        the multigrid preconditioner (Galerkin coarse kappa^2); a positive value
+        makes the preconditioner use that one constant kappa instead.
+        set_coefficients() restores the constants."""
         torch = _torch()
         nc = self.n ** 3
 
@@ -297,11 +298,6 @@ class Box:
                 raise ValueError(f"{name} must have n^3 = {nc} entries")
             return torch.as_tensor(arr).to(self.device)
 
-        if kappa is not None and kappa_ref is None:
-            if isinstance(kappa, torch.Tensor) and kappa.is_cuda:
-                raise ValueError("kappa_ref is required with a device kappa tensor")
-            k = np.asarray(kappa, dtype=np.float64)
-            kappa_ref = math.sqrt(float(k.min()) * float(k.max()))
         tk, tg = dev(kappa, "kappa"), dev(g, "g")
         _abi.check(_abi.lib().spde_set_coefficients(self._hh.h, _ptr(tk), _ptr(tg),
                                                     float(kappa_ref or 0.0)))
@@ -309,16 +305,20 @@ class Box:
         self.kappa_ref = kappa_ref
 
     # -- sampling ---------------------------------------------------------
-    def sample(self, xi, u_tet=True, u_box=False, sigma=False, relres=False, allow_notconv=False):
+    def sample(self, xi, u_tet=True, u_box=False, sigma=False, relres=False, allow_notconv=False,
+               allow_failed=False):
         """Fields for the noise batch xi [B, n^3] (float64, on the device).
 
         Returns a dict with "u_tet" [B, n_tet] (if a mesh is set and u_tet),
         "u_box" [B, n^3], "sigma" [B, 3 n^2 (n+1)], "iters" (numpy int32 [B]),
-        "relres" (numpy float64 [B]) and "status"."""
+        "relres" (numpy float64 [B]) and "status".  allow_notconv /
+        allow_failed return the outputs with SPDE_ENOTCONV / SPDE_EFAILED
+        instead of raising (a failed sample's fields are NaN, the others are
+        valid)."""
         B = xi.shape[0]
         _check_dev_f64(xi, (B, self.n ** 3), "xi")
         return self._run(B, lambda *a: _abi.lib().spde_sample(self._hh.h, B, _ptr(xi), *a),
-                         u_tet, u_box, sigma, relres, allow_notconv)
+                         u_tet, u_box, sigma, relres, allow_notconv, allow_failed)
 
     def sample_warm(self, xi, u_coarse, u_tet=True, u_box=False, sigma=False, relres=False,
                     allow_notconv=False):
@@ -342,7 +342,7 @@ class Box:
             self._hh.h, B, int(seed) & _U64, int(event0) & _U64, int(bool(coupled)), *a),
             u_tet, u_box, sigma, relres, allow_notconv)
 
-    def _run(self, B, call, u_tet, u_box, sigma, relres, allow_notconv):
+    def _run(self, B, call, u_tet, u_box, sigma, relres, allow_notconv, allow_failed=False):
         torch = _torch()
         nc = self.n ** 3
         out = {}
@@ -356,7 +356,7 @@ class Box:
             st = call(_ptr(t_tet), _ptr(t_box), _ptr(t_sig), _stream_ptr(self.device),
                       iters.ctypes.data_as(C.c_void_p),
                       rel.ctypes.data_as(C.c_void_p) if rel is not None else None)
-        allow = (SPDE_OK, SPDE_ENOTCONV) if allow_notconv else (SPDE_OK,)
+        allow = (SPDE_OK,) + ((SPDE_ENOTCONV,) if allow_notconv else ()) + ((SPDE_EFAILED,) if allow_failed else ())
         _abi.check(st, allow)
         out["status"] = st
         if t_tet is not None:
@@ -382,6 +382,22 @@ class Box:
         with torch.cuda.device(self.device):
             _abi.check(_abi.lib().spde_apply_operator(self._hh.h, B, _ptr(x_sigma), _ptr(x_u), _ptr(ys), _ptr(yu),
                                                       _stream_ptr(self.device)))
+        return ys, yu
+
+    def apply_operator_precond(self, x_sigma, x_u):
+        """y = A blkdiag(P_f diag(M), I) x through the production operator pass:
+        the handle's face block P_f (diag(M)^-1 or the Neumann series) and the
+        multigrid precision for x_u (float32 in mixed precision)."""
+        torch = _torch()
+        B = x_u.shape[0]
+        nf = 3 * self.n * self.n * (self.n + 1)
+        _check_dev_f64(x_sigma, (B, nf), "x_sigma")
+        _check_dev_f64(x_u, (B, self.n ** 3), "x_u")
+        ys = torch.empty_like(x_sigma)
+        yu = torch.empty_like(x_u)
+        with torch.cuda.device(self.device):
+            _abi.check(_abi.lib().spde_apply_operator_precond(self._hh.h, B, _ptr(x_sigma), _ptr(x_u), _ptr(ys),
+                                                              _ptr(yu), _stream_ptr(self.device)))
         return ys, yu
 
     def apply_vcycle(self, r):

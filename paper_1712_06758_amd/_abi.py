@@ -48,6 +48,7 @@ SIGNATURES = {
     "spde_set_coefficients": (C.c_int, [_vp, _vp, _vp, C.c_double]),
     "spde_philox4x64": (C.c_int, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64, _vp, _vp]),
     "spde_apply_operator": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp, _vp]),
+    "spde_apply_operator_precond": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp, _vp]),
     "spde_apply_vcycle": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "spde_apply_transfer": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "spde_set_graphs": (C.c_int, [_vp, C.c_int]),

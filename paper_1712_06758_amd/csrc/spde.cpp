@@ -100,6 +100,10 @@ struct Ctx {
   Fields F{};
   void* mgb[kMaxLevels] = {};   // restricted right-hand sides per level (l >= 1)
   void* mge[kMaxLevels] = {};   // level corrections (l >= 1)
+  void* mgd[kMaxLevels] = {};   // cell-wise diagonal of S~ per level (shared by the slots)
+  void* mgdi[kMaxLevels] = {};  // and its reciprocal
+  bool mg_cellwise = false;     // the kappa field enters the multigrid (Galerkin coarse kappa^2)
+  bool mg_dirty = false;        // the level diagonals must be rebuilt before the next solve
   double* resid_out = nullptr;  // [max_batch]
   hipStream_t own_stream = nullptr;
   hipStream_t aux_stream = nullptr;   // second half of a split batch
@@ -160,6 +164,8 @@ void set_level(Level& L, int m, double kappa) {
   L.c2 = 2.0 * rho1 / dl;
   L.cA = L.c1 * L.c0 + L.c2 * (1.0 - L.c0);
   L.cB = L.c2 * L.a * L.c0;
+  L.dg = nullptr;
+  L.dgi = nullptr;
 }
 
 size_t coarse_bytes(const Ctx* c, int top) {
@@ -171,6 +177,7 @@ size_t coarse_bytes(const Ctx* c, int top) {
 void plan_hierarchy(Ctx* c) {
   c->nlev = 0;
   for (int m = c->n; m >= 1; m >>= 1) set_level(c->lv[c->nlev++], m, c->kappa_pre);
+  c->mg_dirty = c->mg_cellwise;   // level diagonals (if any) are rebuilt before the next solve
   // persistent kernel: the largest levels (below the finest) that fit in LDS, at most 16^3
   int top = c->nlev - 1;
   for (int l = 1; l < c->nlev; ++l) {
@@ -212,6 +219,10 @@ size_t layout(Ctx* c, char* base) {
   for (int l = 1; l <= c->top && l < c->nlev; ++l) {
     c->mgb[l] = take(B * c->lv[l].nc * c->szm());
     c->mge[l] = take(B * c->lv[l].nc * c->szm());
+  }
+  for (int l = 0; l < c->nlev; ++l) {
+    c->mgd[l] = take(c->lv[l].nc * c->szm());
+    c->mgdi[l] = take(c->lv[l].nc * c->szm());
   }
   c->F.part_up = (double*)take(B * (size_t)c->nb_up0 * 2 * 8);
   c->F.part_pb = (double*)take(B * (size_t)c->nb_pb * 2 * 8);
@@ -284,6 +295,17 @@ double slot_bytes(const Ctx* c, int kid, int level, int iter, int wmode_active) 
   }
 }
 
+// Tile shapes a level's kernels run with: the tuned ones, except that the
+// cell-wise-diagonal kernels exist only in the pipelined column shapes (10-17).
+int eff_down(const Ctx* c, int l) {
+  const int s = c->shape_down[l];
+  return (c->lv[l].dg && s < 10) ? 16 : s;
+}
+int eff_up(const Ctx* c, int l) {
+  const int s = c->shape_up[l];
+  return (c->lv[l].dg && s < 10) ? 17 : s;
+}
+
 // ---- one MINRES iteration (all kernels), enqueued on st ------------------------
 
 // The slots [s0, s0 + batch) of the context: device pointers advanced to slot
@@ -308,7 +330,7 @@ View make_view(const Ctx* c, int s0) {
     V.F.w[p] += (int64_t)s0 * nc;
   }
   V.F.x += (int64_t)s0 * nc;
-  V.F.part_up += (int64_t)s0 * tiles_for(c->shape_up[0], c->n) * 2;
+  V.F.part_up += (int64_t)s0 * tiles_for(eff_up(c, 0), c->n) * 2;
   V.F.part_pb += (int64_t)s0 * c->nb_pb;
   V.F.sc += s0;
   for (int l = 1; l < c->nlev; ++l) {
@@ -324,11 +346,11 @@ spde_status enqueue_vcycle(Ctx* c, const View& V, int batch, hipStream_t st, int
   const int s0 = V.s0;
   {
     Timed t(c, KID_MG_DOWN_FINE, iter, st, 0, s0, batch);
-    HIPCHK(launch_mg_down(f64, c->shape_down[0], true, b0, b1, V.mgb[1], c->lv[0], batch, sc, st));
+    HIPCHK(launch_mg_down(f64, eff_down(c, 0), true, b0, b1, V.mgb[1], c->lv[0], batch, sc, st));
   }
   for (int l = 1; l < c->top; ++l) {
     Timed t(c, KID_MG_DOWN, iter, st, l, s0, batch);
-    HIPCHK(launch_mg_down(f64, c->shape_down[l], false, V.mgb[l], V.mgb[l], V.mgb[l + 1], c->lv[l], batch, sc, st));
+    HIPCHK(launch_mg_down(f64, eff_down(c, l), false, V.mgb[l], V.mgb[l], V.mgb[l + 1], c->lv[l], batch, sc, st));
   }
   {
     Timed t(c, KID_MG_COARSE, iter, st, 0, s0, batch);
@@ -336,12 +358,12 @@ spde_status enqueue_vcycle(Ctx* c, const View& V, int batch, hipStream_t st, int
   }
   for (int l = c->top - 1; l >= 1; --l) {
     Timed t(c, KID_MG_UP, iter, st, l, s0, batch);
-    HIPCHK(launch_mg_up(f64, c->shape_up[l], false, V.mgb[l], V.mgb[l], V.mge[l + 1], V.mge[l], V.mge[l],
+    HIPCHK(launch_mg_up(f64, eff_up(c, l), false, V.mgb[l], V.mgb[l], V.mge[l + 1], V.mge[l], V.mge[l],
                         c->lv[l], batch, sc, nullptr, nullptr, nullptr, c->box, st));
   }
   {
     Timed t(c, KID_MG_UP_FINE, iter, st, 0, s0, batch);
-    HIPCHK(launch_mg_up(f64, c->shape_up[0], true, b0, b1, V.mge[1], o0, o1, c->lv[0], batch, sc,
+    HIPCHK(launch_mg_up(f64, eff_up(c, 0), true, b0, b1, V.mge[1], o0, o1, c->lv[0], batch, sc,
                         V.F.vs[0], V.F.vs[1], part, c->box, st));
   }
   return SPDE_OK;
@@ -353,7 +375,7 @@ spde_status enqueue_vpart(Ctx* c, const View& V, int batch, hipStream_t st, int 
                                  V.F.part_up);
   if (s != SPDE_OK) return s;
   Timed t(c, KID_SCALAR, iter, st, 0, V.s0, batch);
-  HIPCHK(launch_scalar(V.F, tiles_for(c->shape_up[0], c->n), c->nb_pb, batch, st));
+  HIPCHK(launch_scalar(V.F, tiles_for(eff_up(c, 0), c->n), c->nb_pb, batch, st));
   return SPDE_OK;
 }
 
@@ -636,6 +658,54 @@ spde_status autotune(Ctx* c, hipStream_t st) {
   return SPDE_OK;
 }
 
+// Cell-wise kappa in the multigrid preconditioner: the reaction diagonal of
+// every level (k2 = (kappa kappa) h^3 on the finest, the Galerkin sum of the 8
+// children on the coarser ones), each level's diagonal D = K + a nn and D^-1
+// in the level precision, and the Chebyshev intervals from kappa_min (the
+// Gershgorin bound (k2 + 12 a) / (k2 + 6 a) of D^-1 S~ is largest where k2 is
+// smallest, and every level's k2 is at least kappa_min^2 H^3).  The float64
+// chain is built in a Lanczos buffer that no solve uses between calls.
+spde_status prepare_mg_coeffs(Ctx* c, hipStream_t st) {
+  if (!c->mg_dirty) return SPDE_OK;
+  if (!c->mg_cellwise || !c->box.kap) { c->mg_dirty = false; return SPDE_OK; }
+  const int64_t nc = c->box.nc;
+  double* k2 = c->F.vs[0];                       // [sum of the level sizes] float64 scratch
+  double* k2l[kMaxLevels];
+  int64_t off = 0;
+  for (int l = 0; l < c->nlev; ++l) { k2l[l] = k2 + off; off += c->lv[l].nc; }
+  double* mins = k2 + off;                       // block minima of kappa (the chain needs < 8/7 nc)
+  HIPCHK(launch_mg_k2_fine(c->box.kap, c->box.h3, k2l[0], nc, st));
+  for (int l = 1; l < c->nlev; ++l) HIPCHK(launch_mg_k2_coarsen(k2l[l - 1], k2l[l], c->lv[l - 1].m, st));
+  // kappa_min by repeated block minima until at most 4096 values remain
+  const double* src = c->box.kap;
+  int64_t cnt = nc;
+  double* dst = mins;
+  while (true) {
+    HIPCHK(launch_block_min(src, cnt, dst, st));
+    cnt = (cnt + kBlock - 1) / kBlock;
+    src = dst;
+    if (cnt <= 4096) break;
+    dst = dst + cnt;
+  }
+  HIPCHK(hipMemcpyAsync(c->host_res, src, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double kmin = c->host_res[0];
+  for (int64_t i = 1; i < cnt; ++i) kmin = std::min(kmin, c->host_res[i]);
+  if (!(kmin > 0.0) || !std::isfinite(kmin))
+    return fail(SPDE_EINVAL, "the kappa field must be positive and finite (minimum %g)", kmin);
+  for (int l = 0; l < c->nlev; ++l) {
+    set_level(c->lv[l], c->lv[l].m, kmin);
+    HIPCHK(launch_mg_diag(c->fp64(), k2l[l], c->lv[l].m, c->lv[l].a, c->mgd[l], c->mgdi[l], st));
+    c->lv[l].dg = c->mgd[l];
+    c->lv[l].dgi = c->mgdi[l];
+  }
+  for (int l = c->top; l < c->nlev; ++l) c->cp.lv[l - c->top] = c->lv[l];
+  c->kappa_pre = kmin;
+  c->mg_dirty = false;
+  drop_graphs(c);
+  return SPDE_OK;
+}
+
 }  // namespace
 
 // =============================================================================
@@ -697,14 +767,17 @@ spde_status spde_configure(spde_handle h, spde_precision prec, double rtol, int 
 spde_status spde_set_coefficients(spde_handle h, const double* kappa_dev, const double* g_dev, double kappa_ref) {
   Ctx* c = reinterpret_cast<Ctx*>(h);
   if (!c) return fail(SPDE_EINVAL, "null handle");
-  if (kappa_dev && !(kappa_ref > 0.0 && std::isfinite(kappa_ref)))
-    return fail(SPDE_EINVAL, "kappa_ref must be positive and finite with a kappa field");
-  if (!kappa_dev && kappa_ref != 0.0 && !(kappa_ref > 0.0 && std::isfinite(kappa_ref)))
+  if (kappa_ref != 0.0 && !(kappa_ref > 0.0 && std::isfinite(kappa_ref)))
     return fail(SPDE_EINVAL, "kappa_ref must be 0 or positive and finite");
   drop_graphs(c);   // kernel arguments change
   c->box.kap = kappa_dev;
   c->box.gfld = g_dev;
-  c->kappa_pre = kappa_dev ? kappa_ref : (kappa_ref > 0.0 ? kappa_ref : c->kappa);
+  // kappa field with kappa_ref = 0: the multigrid takes the cell-wise kappa
+  // (its level diagonals are built before the next solve); otherwise one
+  // constant kappa
+  c->mg_cellwise = kappa_dev && kappa_ref == 0.0;
+  c->mg_dirty = c->mg_cellwise;
+  c->kappa_pre = kappa_ref > 0.0 ? kappa_ref : c->kappa;
   // new level coefficients of the preconditioner; shapes, tiles and layout stay
   for (int l = 0; l < c->nlev; ++l) set_level(c->lv[l], c->lv[l].m, c->kappa_pre);
   for (int l = c->top; l < c->nlev; ++l) c->cp.lv[l - c->top] = c->lv[l];
@@ -892,6 +965,8 @@ spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_de
   const double scale = -c->g * std::pow(bx.h, 1.5);
   s = autotune(c, st);
   if (s != SPDE_OK) return s;
+  s = prepare_mg_coeffs(c, st);
+  if (s != SPDE_OK) return s;
   // the load F_u: the caller's noise, or the generated noise drawn again into
   // a Lanczos buffer that no running solve uses
   const double* xi_res = src.xi;
@@ -934,12 +1009,14 @@ spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_de
     HIPCHK(launch_inject_coarse(warm_uc, c->F.x, bx.n, batch, st));
     s = residual();
     if (s != SPDE_OK) return s;
-    double worst = 0.0;
-    for (int b = 0; b < batch; ++b)
-      if (std::isfinite(c->host_res[b])) worst = std::max(worst, c->host_res[b]);
-    const double tol = worst > 0.0 ? std::min(0.5, std::max(c->rtol, c->rtol / worst)) : c->rtol;
+    // each sample's own tolerance, so that its result does not depend on the batch
+    for (int b = 0; b < batch; ++b) {
+      const double r0 = c->host_res[b];
+      c->host_res[b] = std::isfinite(r0) && r0 > 0.0 ? std::min(0.5, std::max(c->rtol, c->rtol / r0)) : c->rtol;
+    }
+    HIPCHK(hipMemcpyAsync(c->resid_out, c->host_res, batch * sizeof(double), hipMemcpyHostToDevice, st));
     Timed t(c, KID_INIT, 0, st);
-    HIPCHK(launch_init_correction(c->F, bx, batch, tol, c->max_iter, st));
+    HIPCHK(launch_init_correction(c->F, bx, batch, c->resid_out, c->max_iter, st));
   }
   const bool graphs = c->use_graphs && c->timing != 1 && st != nullptr;
   // A batch of 8 or more runs as two halves on two streams, so that the
@@ -1012,20 +1089,26 @@ spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_de
       res_final = true;
       std::vector<char> refine(batch, 0);
       bool need_any = false;
-      double worst = 0.0;
       for (int b = 0; b < batch; ++b) {
         if (bad[b] || c->host_res[b] <= c->refine_target) continue;
         refine[b] = 1;
         need_any = true;
-        if (std::isfinite(c->host_res[b])) worst = std::max(worst, c->host_res[b]);
       }
       if (!need_any || pass >= c->refine_max) break;
-      // the pass has to reduce its residual by target / worst only (a factor
-      // of 10 to spare); never tighter than the configured rtol, which the
-      // preconditioned MINRES is known to reach
-      const double tol_pass = worst > 0.0 ? std::min(0.5, std::max(c->rtol, 0.1 * c->refine_target / worst))
-                                          : c->rtol;
-      HIPCHK(launch_init_correction(c->F, bx, batch, tol_pass, c->max_iter, st));
+      // A sample's pass has to reduce its residual by target / residual only (a
+      // factor of 10 to spare), never tighter than the configured rtol, which
+      // the preconditioned MINRES is known to reach.  Each sample takes its own
+      // tolerance, so that its result does not depend on the batch.
+      std::vector<double> tols(batch);
+      for (int b = 0; b < batch; ++b) {
+        const double r = c->host_res[b];
+        tols[b] = refine[b] && std::isfinite(r) && r > 0.0
+                      ? std::min(0.5, std::max(c->rtol, 0.1 * c->refine_target / r))
+                      : c->rtol;
+      }
+      std::copy(tols.begin(), tols.end(), c->host_res);
+      HIPCHK(hipMemcpyAsync(c->resid_out, c->host_res, batch * sizeof(double), hipMemcpyHostToDevice, st));
+      HIPCHK(launch_init_correction(c->F, bx, batch, c->resid_out, c->max_iter, st));
       for (int b = 0; b < batch; ++b)
         if (!refine[b]) HIPCHK(launch_set_state(c->F.sc, b, 1, ST_DONE, st));
       if (split) {   // the second stream's half starts after the pass's set-up
@@ -1158,6 +1241,8 @@ spde_status spde_slots_reset(spde_handle h, int nslots, void* stream) {
   HIPCHK(hipSetDevice(c->device));
   hipStream_t st = pick_stream(c, stream);
   s = autotune(c, st);
+  if (s != SPDE_OK) return s;
+  s = prepare_mg_coeffs(c, st);
   if (s != SPDE_OK) return s;
   HIPCHK(launch_set_state(c->F.sc, 0, nslots, ST_IDLE, st));
   return SPDE_OK;
@@ -1299,6 +1384,24 @@ spde_status spde_apply_operator(spde_handle h, int batch, const double* x_sigma_
   return SPDE_OK;
 }
 
+spde_status spde_apply_operator_precond(spde_handle h, int batch, const double* x_sigma_dev, const double* x_u_dev,
+                                        double* y_sigma_dev, double* y_u_dev, void* stream) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  spde_status s = check_ready(c);
+  if (s != SPDE_OK) return s;
+  if (batch < 1 || batch > c->max_batch) return fail(SPDE_EINVAL, "batch out of range");
+  if (!x_sigma_dev || !x_u_dev || !y_sigma_dev || !y_u_dev) return fail(SPDE_EINVAL, "null pointer");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = pick_stream(c, stream);
+  // v_sigma = diag(M) x_sigma and zhat = x_u in the solver's own buffers, so
+  // that the pass forms z_sigma = P_f v_sigma with the handle's face block
+  HIPCHK(launch_ext_to_int_zhat(x_sigma_dev, x_u_dev, c->F, c->box, batch, c->fp64(), st));
+  HIPCHK(launch_probe_scalars(c->F.sc, batch, st));
+  HIPCHK(launch_operator(c->fp64(), c->F, c->box, batch, st));
+  HIPCHK(launch_int_to_ext(c->F, y_sigma_dev, y_u_dev, c->box, batch, st));
+  return SPDE_OK;
+}
+
 spde_status spde_apply_vcycle(spde_handle h, int batch, const double* r_dev, double* z_dev, void* stream) {
   Ctx* c = reinterpret_cast<Ctx*>(h);
   spde_status s = check_ready(c);
@@ -1309,6 +1412,8 @@ spde_status spde_apply_vcycle(spde_handle h, int batch, const double* r_dev, dou
   hipStream_t st = pick_stream(c, stream);
   void* out = c->fp64() ? (void*)z_dev : c->F.z[0];
   s = autotune(c, st);
+  if (s != SPDE_OK) return s;
+  s = prepare_mg_coeffs(c, st);
   if (s != SPDE_OK) return s;
   // the finest up kernel always writes partial sums: give it the solver's buffer
   s = enqueue_vcycle(c, make_view(c, 0), batch, st, 0, r_dev, r_dev, out, out, nullptr, c->F.part_up);

@@ -104,16 +104,23 @@ __host__ __device__ inline double cell_k2h3(const Box& b, int64_t c) {
   return b.kap ? cell_k2h3<true>(b, c) : b.k2h3;
 }
 
-// One multigrid level: operator S~ = k2 I + a L (L the Neumann graph
-// Laplacian), Chebyshev smoother coefficients of the degree-2 polynomial.
+// One multigrid level: operator S~ = K + a L (L the Neumann graph Laplacian,
+// K = k2 I, or with cell-wise kappa the diagonal of the level's kappa_c^2 H^3),
+// Chebyshev smoother coefficients of the degree-2 polynomial.
 struct Level {
   int m;             // cells per edge
   int64_t nc;        // m^3
-  double k2;         // kappa^2 H^3
+  double k2;         // kappa^2 H^3 (cell-wise kappa: kappa_min^2 H^3, which bounds the spectrum)
   double a;          // 3 H / 2
   double c0, c1, c2; // y = c0 D^-1 r ; x = c1 y + c2 D^-1 (r - A y)
   double cA, cB;     // pre-smoothing from zero in terms of bhat = D^-1 b:
                      // x = cA bhat + (cB / d) * sum_nbr bhat
+  // Cell-wise diagonal D = K + a diag(neighbour count) of the level and its
+  // reciprocal ([m^3] in the level precision, shared by all samples), or null
+  // when kappa is constant.  The coarse K is the Galerkin one: each coarse
+  // cell's k2 is the sum of its 8 children's.
+  const void* dg;
+  const void* dgi;
 };
 
 struct CoarseParams {
@@ -206,14 +213,27 @@ hipError_t launch_resid(const double* sig, const double* u, const double* xi, do
 // Warm start: x[slot] = the (n/2)^3 field uc[slot] injected into its children.
 hipError_t launch_inject_coarse(const double* uc, double* x, int n, int batch, hipStream_t st);
 // Refinement pass: v_1 = [0; the load already in vu[1]], scalars reset with FL_ACCUM.
-hipError_t launch_init_correction(const Fields& F, const Box& bx, int batch, double tol, int max_iter,
+// The tolerance of slot b is tols[b] (device array [batch]).
+hipError_t launch_init_correction(const Fields& F, const Box& bx, int batch, const double* tols, int max_iter,
                                   hipStream_t st);
 hipError_t launch_spmm(const int64_t* rp, const int32_t* ci, const double* cv, const double* u, double* out,
                        int64_t ntet, int64_t nnz, int64_t nc, int batch, const int32_t* order, hipStream_t st);
 hipError_t launch_restrict_noise(const double* xf, double* xc, int nf, int batch, hipStream_t st);
 hipError_t launch_ext_to_int(const double* xs, const double* xu, const Fields& F, const Box& bx, int batch,
                              hipStream_t st);
+// Same, with zhat = x_u written to the solver's own z buffer in the multigrid
+// precision (float32 unless z_fp64).
+hipError_t launch_ext_to_int_zhat(const double* xs, const double* xu, const Fields& F, const Box& bx, int batch,
+                                  bool z_fp64, hipStream_t st);
 hipError_t launch_int_to_ext(const Fields& F, double* ys, double* yu, const Box& bx, int batch, hipStream_t st);
 hipError_t launch_probe_scalars(Scalars* sc, int batch, hipStream_t st);
+// Cell-wise multigrid coefficients: k2 = (kappa kappa) h^3 on the finest level,
+// the sum of the 8 children on each coarser one (float64), then the level's
+// diagonal k2 + a nn and its reciprocal in the level precision.
+hipError_t launch_mg_k2_fine(const double* kap, double h3, double* k2, int64_t nc, hipStream_t st);
+hipError_t launch_mg_k2_coarsen(const double* k2f, double* k2c, int mf, hipStream_t st);
+hipError_t launch_mg_diag(bool fp64, const double* k2, int m, double a, void* dg, void* dgi, hipStream_t st);
+// Per-block minima of v[0, n) into out[(n + 255) / 256].
+hipError_t launch_block_min(const double* v, int64_t n, double* out, hipStream_t st);
 hipError_t launch_f32_to_f64(const float* s, double* d, int64_t count, hipStream_t st);
 }  // namespace spde

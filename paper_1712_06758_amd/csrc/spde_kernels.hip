@@ -51,9 +51,11 @@ __global__ __launch_bounds__(kBlock) void k_init(Fields F, Box bx, const double*
 }
 
 // Refinement pass (iterative refinement in float64 around the whole solve):
-// v_1 = [0; r] with r = F - A U already in vu[1], MINRES state reset, and
-// FL_ACCUM so that the pass adds its correction to x = U.
-__global__ __launch_bounds__(kBlock) void k_init_correction(Fields F, Box bx, int nb, double tol, int max_iter) {
+// v_1 = [0; r] with r = F - A U already in vu[1], MINRES state reset with the
+// slot's own tolerance tols[slot], and FL_ACCUM so that the pass adds its
+// correction to x = U.
+__global__ __launch_bounds__(kBlock) void k_init_correction(Fields F, Box bx, int nb, const double* __restrict__ tols,
+                                                            int max_iter) {
   const int slot = blockIdx.x / nb;
   const int blk = blockIdx.x - slot * nb;
   const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
@@ -63,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_init_correction(Fields F, Box bx, in
     F.vs[1][face_off(slot, 2, bx.nc) + c] = 0.0;
   }
   if (blk == 0 && threadIdx.x == 0) {
-    init_scalars(F, slot, tol, max_iter);
+    init_scalars(F, slot, tols[slot], max_iter);
     F.sc[slot].flags = FL_ACCUM;
   }
 }
@@ -374,6 +376,27 @@ __global__ __launch_bounds__(kBlock) void k_restrict_noise(const double* __restr
 // layout conversions for the operator check: external -> internal Lanczos form
 // (v_sigma = x_sigma / q so that q v_sigma = x_sigma, zhat = x_u), and back.
 
+// zhat = x_u into the solver's z[0] in the multigrid precision TZ, v_sigma =
+// x_sigma / q as above (the check of the production operator instances).
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void k_ext_to_int_zhat(const double* __restrict__ xs,
+                                                            const double* __restrict__ xu, Fields F, Box bx, int nb) {
+  const int slot = blockIdx.x / nb, blk = blockIdx.x - slot * nb;
+  const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
+  const int64_t nc = bx.nc;
+  const int n = bx.n;
+  if (c >= nc) return;
+  const int i = (int)(c % n), j = (int)((c / n) % n), k = (int)(c / bx.n2);
+  const int64_t nf = bx.n2 * (n + 1);
+  const double* e = xs + (int64_t)slot * 3 * nf;
+  const double iq = 1.0 / bx.q;
+  F.vs[0][face_off(slot, 0, nc) + c] = i > 0 ? e[i + (int64_t)(n + 1) * (j + (int64_t)n * k)] * iq : 0.0;
+  F.vs[0][face_off(slot, 1, nc) + c] = j > 0 ? e[nf + i + (int64_t)n * (j + (int64_t)(n + 1) * k)] * iq : 0.0;
+  F.vs[0][face_off(slot, 2, nc) + c] = k > 0 ? e[2 * nf + i + (int64_t)n * (j + (int64_t)n * k)] * iq : 0.0;
+  reinterpret_cast<TZ*>(F.z[0])[cell_off(slot, nc) + c] = (TZ)xu[cell_off(slot, nc) + c];
+  F.vu[0][cell_off(slot, nc) + c] = 0.0;
+}
+
 __global__ __launch_bounds__(kBlock) void k_ext_to_int(const double* __restrict__ xs, const double* __restrict__ xu,
                                                        Fields F, Box bx, int nb) {
   const int slot = blockIdx.x / nb, blk = blockIdx.x - slot * nb;
@@ -429,6 +452,65 @@ __global__ void k_tune_scalars(Scalars* sc, int batch) {
   Scalars v{};
   v.state = ST_ACTIVE; v.pit = 4; v.it = 4; v.wmode = 2; v.zs = 1.0;
   sc[s] = v;
+}
+
+// ---------------------------------------------------------------------------
+// cell-wise kappa in the multigrid hierarchy (set-up, once per coefficient field)
+
+// Finest level: k2_c = (kappa_c kappa_c) h^3, the reaction term of the cell row
+// with the operator's rounding.
+__global__ __launch_bounds__(kBlock) void k_mg_k2_fine(const double* __restrict__ kap, double h3,
+                                                       double* __restrict__ k2, int64_t nc) {
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c < nc) k2[c] = (kap[c] * kap[c]) * h3;
+}
+
+// Galerkin reaction term of the next coarser level: P^T diag(k2_f) P with the
+// P0 injection P is diagonal, each coarse cell holding the sum of its 8
+// children (the coarse kappa^2 is the children's mean, eq. ml-linsys).
+__global__ __launch_bounds__(kBlock) void k_mg_k2_coarsen(const double* __restrict__ k2f,
+                                                          double* __restrict__ k2c, int mf) {
+  const int mc = mf >> 1;
+  const int64_t C = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (C >= (int64_t)mc * mc * mc) return;
+  const int I = (int)(C % mc), J = (int)((C / mc) % mc), K = (int)(C / ((int64_t)mc * mc));
+  double acc = 0.0;
+#pragma unroll
+  for (int ch = 0; ch < 8; ++ch) {
+    const int i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
+    acc += k2f[i + (int64_t)mf * (j + (int64_t)mf * k)];
+  }
+  k2c[C] = acc;
+}
+
+// Diagonal of S~ = K + a L on an m^3 level and its reciprocal, formed in
+// float64 and rounded once to the level precision.
+template <typename TM>
+__global__ __launch_bounds__(kBlock) void k_mg_diag(const double* __restrict__ k2, int m, double a,
+                                                    TM* __restrict__ dg, TM* __restrict__ dgi) {
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= (int64_t)m * m * m) return;
+  const int i = (int)(c % m), j = (int)((c / m) % m), k = (int)(c / ((int64_t)m * m));
+  const double d = k2[c] + a * (double)nnbr(i, j, k, m);
+  dg[c] = (TM)d;
+  dgi[c] = (TM)(1.0 / d);
+}
+
+// Per-block minimum.
+__global__ __launch_bounds__(kBlock) void k_block_min(const double* __restrict__ v, int64_t n,
+                                                      double* __restrict__ out) {
+  __shared__ double red[kBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double x = i < n ? v[i] : INFINITY;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < kBlock / 64; ++w) r = fmin(r, red[w]);
+    out[blockIdx.x] = r;
+  }
 }
 
 template <typename TS, typename TD>

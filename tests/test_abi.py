@@ -129,8 +129,9 @@ def test_set_coefficients_validation(lib):
     st, h = setup(lib, 16)
     assert st == 0
     fake = C.c_void_p(0x1000)          # stored only; nothing reads it without a sampling call
-    assert L.spde_set_coefficients(h, fake, None, 0.0) == -1        # kappa field needs kappa_ref
+    assert L.spde_set_coefficients(h, fake, None, 0.0) == 0         # cell-wise kappa in the multigrid
     assert L.spde_set_coefficients(h, fake, None, float("nan")) == -1
+    assert L.spde_set_coefficients(h, fake, None, -1.0) == -1
     assert L.spde_set_coefficients(h, None, None, -2.0) == -1
     assert L.spde_set_coefficients(h, fake, fake, 7.0) == 0
     assert L.spde_set_coefficients(h, None, None, 0.0) == 0

@@ -57,3 +57,54 @@ def test_alone_equals_mix_and_oracle():
             Pc = T.build_pi(xyz, tets, n // 2, rows=rows)
             got = r.parts[1].result.cpu().numpy()[rows]
             assert np.abs(got - Pc @ u_c).max() <= 1e-9 * np.abs(Pc @ u_c).max()
+
+
+def test_mixed_precision_serving_with_128_level():
+    """Mixed precision (float32 multigrid), levels 64^3 and 128^3: every 128^3
+    request carries its coupled 64^3 coarse part.  24 requests arrive together
+    and over a short window (slots refill mid-flight); each of them, re-run
+    alone on a server whose 128^3 engine runs on a CU-masked stream, gives
+    bitwise the same tet values for every part.  Two 128^3 requests (fine and
+    coarse parts) against the oracle at the mixed bar: volume-weighted
+    relative L2 on 10^4 sampled tets of the level's mesh."""
+    import torch
+    from paper_1712_06758_amd.serve import build_gpu_server
+    from tests import oracle_pool
+    say("mixed-precision serving alone vs mix, levels 64/128")
+    levels = (64, 128)
+    slots = {64: 8, 128: 4}
+    srv = build_gpu_server(levels, 0.05, "mixed", slots=slots, keep_results=True, poll=2)
+    arr = sorted([(0.0, 128, i) for i in range(4)] + [(0.0, 64, 100 + i) for i in range(4)] +
+                 [(0.003 * i, 128 if i % 2 else 64, 200 + i) for i in range(16)])
+    rep = srv.run(arr, time_limit=180)
+    say(f"mixed serving report {rep}")
+    assert rep["completed"] == len(arr)
+    mix = {r.seed: r for r in srv.done}
+    logged = sorted(mix)
+    assert len(logged) >= 20
+    alone = build_gpu_server(levels, 0.05, "mixed", slots=slots, keep_results=True, poll=2,
+                             reserve_cus=32, big_level=128)
+    for seed in logged:
+        alone.run([(0.0, seed[0], seed[1])], time_limit=60)
+        a = alone.done[-1]
+        b = mix[seed]
+        assert a.seed == b.seed and len(a.parts) == len(b.parts)
+        for pa, pb in zip(a.parts, b.parts):
+            assert pa.kind == pb.kind
+            assert torch.equal(pa.result, pb.result), (seed, pa.kind)
+    kappa = 20.0
+    g = np.sqrt(8 * np.pi * kappa)
+    big = [s for s in logged if s[0] == 128][:2]
+    assert len(big) == 2
+    rows, Pf, vol = oracle_pool.transfer_rows("serve128")
+    rows_c, Pc, vol_c = oracle_pool.transfer_rows("serve128", 64)
+    for seed in big:
+        r = mix[seed]
+        key = r.noise
+        xi = PH.noise(128, key.seed, key.event)
+        u_f = S.solve_u(128, kappa, g, xi)
+        u_c = S.solve_u(64, kappa, g, noise.restrict(128, xi))
+        ef = oracle_pool.volume_weighted_rel_l2(r.parts[0].result.cpu().numpy()[rows], Pf @ u_f, vol)
+        ec = oracle_pool.volume_weighted_rel_l2(r.parts[1].result.cpu().numpy()[rows_c], Pc @ u_c, vol_c)
+        say(f"  request {seed}: fine part {ef:.2e}, coarse part {ec:.2e}")
+        assert ef <= 1e-7 and ec <= 1e-7

@@ -241,3 +241,22 @@ def test_coarse_warm_start_saves_little():
     _, it_cold, _ = MR.minres(lambda v: A @ v, F, Pinv, tol=1e-8)
     _, it_warm, _ = MR.minres(lambda v: A @ v, F, Pinv, tol=1e-8 * nb / nr, x0=x0)
     assert it_cold - 2 <= it_warm <= it_cold
+
+
+@pytest.mark.parametrize("n", [4, 5, 7])
+def test_face_block_series_spectrum_closed_form(n):
+    """P_f M has the eigenvalues 1 + s^3 with s = cos(pi k / n) / 2, k = 1..n-1,
+    each 3 n^2 times: on a grid line M = diag(M) (I + S) with S the
+    shift (v_{g-1} + v_{g+1}) / 4, whose eigenvalues are those s, and the
+    second-order series gives (I - S + S^2)(I + S) = I + S^3.  A dropped or
+    mis-signed term changes the spectrum (e.g. I + 2S + 2S^2 + S^3)."""
+    from oracle import minres as MR
+    ops = D.assemble(n)
+    Pf = MR.face_block_series(ops)
+    assert abs(Pf - Pf.T).max() <= 1e-12 * abs(Pf).max()
+    ev = np.sort(np.linalg.eigvals((Pf @ ops["M"]).toarray()).real)
+    s = 0.5 * np.cos(np.pi * np.arange(1, n) / n)
+    ref = np.sort(np.repeat(1.0 + s ** 3, 3 * n * n))
+    np.testing.assert_allclose(ev, ref, rtol=0, atol=1e-12)
+    # symmetric positive definite: eigenvalues of P_f itself are positive
+    assert np.linalg.eigvalsh(Pf.toarray()).min() > 0
