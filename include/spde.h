@@ -155,16 +155,24 @@ spde_status spde_set_transfer(spde_handle h, int64_t n_tet, int64_t nnz,
                               const int64_t* row_ptr_dev, const int32_t* col_dev,
                               const double* val_dev);
 
-/* Visiting order of the transfer SpMM: order_host [n_rows] receives the row
- * indices sorted by their first column (cell index), so that neighbouring
- * threads gather neighbouring cells.  Host-only; row_ptr/col as built above. */
-spde_status spde_transfer_row_order(int64_t n_rows, const int64_t* row_ptr_host,
-                                    const int32_t* col_host, int32_t* order_host);
+/* Visiting order of the transfer SpMM.  The product takes the rows in chunks
+ * of spde_transfer_chunk_rows() consecutive rows (so that each sample's
+ * values are stored contiguously) and visits the chunks in an order that
+ * keeps neighbouring chunks together in time, so that the box cells they
+ * share are still cached: order_host [ceil(n_rows / chunk)] receives the
+ * chunk indices sorted by the cell of each chunk's first entry (16 x 16-cell
+ * tiles of the (x, y) plane, then z, then y, then x).  n in [1, 1024] is the
+ * box edge of the matrix's columns; row_ptr/col as built above (host).
+ * Host-only. */
+int spde_transfer_chunk_rows(void);
+spde_status spde_transfer_chunk_order(int n, int64_t n_rows, const int64_t* row_ptr_host,
+                                      const int32_t* col_host, int32_t* order_host);
 
-/* Register a device copy of such an order for the handle's transfer (borrowed;
- * NULL restores the natural order).  Must follow spde_set_transfer.  Results
- * do not depend on the order: each row is computed by one thread. */
-spde_status spde_set_transfer_order(spde_handle h, const int32_t* order_dev);
+/* Register a device copy of such a chunk order for the handle's transfer
+ * (borrowed; NULL: the chunks in index order).  Must follow spde_set_transfer.
+ * Results do not depend on the order: each row's sum is formed the same way
+ * wherever it runs. */
+spde_status spde_set_transfer_chunk_order(spde_handle h, const int32_t* order_dev);
 
 /* ---- the sampler --------------------------------------------------------- */
 
@@ -324,13 +332,23 @@ spde_status spde_slot_finish(spde_handle h, int slot, double* u_box_dev, void* s
 
 /* Stateless CSR SpMM y[b] = A x[b] for b < batch (the transfer apply with an
  * explicit matrix, Sec. "L2-Projection", eq. proj_op).  x [batch][n_cols],
- * y [batch][n_rows]; column indices outside [0, n_cols) are skipped; rows are
- * visited in order_dev (see spde_transfer_row_order) when it is not NULL.
- * Asynchronous on `stream`. */
+ * y [batch][n_rows]; column indices outside [0, n_cols) are skipped; the
+ * row chunks are visited in chunk_order_dev (see spde_transfer_chunk_order)
+ * when it is not NULL, else in index order.  Each row sums its entries in
+ * their stored order, the same for every batch.
+ * The samples are processed in blocks of up to 64, each block first staged
+ * sample-minor (x_t[col][s]) so that one gather of a column brings the whole
+ * block: work_dev (256-byte aligned, caller-owned, at least
+ * spde_csr_apply_work_bytes(n_cols, batch) bytes) holds the staged block; it
+ * may be NULL for batch 1, which needs none.  SPDE_EINVAL for bad sizes, a null
+ * array or a work buffer that is too small.  Asynchronous on `stream`; the
+ * work buffer is in use until the call's work on the stream has finished. */
+size_t spde_csr_apply_work_bytes(int64_t n_cols, int batch);
 spde_status spde_csr_apply(int64_t n_rows, int64_t nnz, const int64_t* row_ptr_dev,
                            const int32_t* col_dev, const double* val_dev, int64_t n_cols,
                            int batch, const double* x_dev, double* y_dev,
-                           const int32_t* order_dev /* nullable */, void* stream);
+                           const int32_t* chunk_order_dev /* nullable */, void* work_dev,
+                           size_t work_bytes, void* stream);
 
 /* ---- operators exposed for verification -------------------------------- */
 
@@ -361,8 +379,10 @@ spde_status spde_apply_operator_precond(spde_handle h, int batch, const double* 
 spde_status spde_apply_vcycle(spde_handle h, int batch, const double* r_dev,
                               double* z_dev, void* stream);
 
-/* u_tet = Pi u_box with the registered transfer.  [batch][n^3] -> [batch][n_tet].
- * Asynchronous on `stream`. */
+/* u_tet = Pi u_box with the registered transfer.  [batch][n^3] -> [batch][n_tet],
+ * batch <= max_batch.  Stages the samples in the bound workspace (as
+ * spde_csr_apply does in its work buffer), so it must not overlap a running
+ * solve or iterating slots of the same handle.  Asynchronous on `stream`. */
 spde_status spde_apply_transfer(spde_handle h, int batch, const double* u_box_dev,
                                 double* u_tet_dev, void* stream);
 

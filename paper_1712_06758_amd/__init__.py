@@ -18,7 +18,7 @@ import numpy as np
 from . import _abi
 from ._abi import SpdeError, SPDE_FP64, SPDE_MIXED, SPDE_OK, SPDE_ENOTCONV, SPDE_EFAILED  # noqa: F401
 
-__all__ = ["Box", "restrict_noise", "noise", "philox4x64", "g_unit_variance", "SpdeError", "build_transfer_host",
+__all__ = ["Box", "csr_apply", "restrict_noise", "noise", "philox4x64", "g_unit_variance", "SpdeError", "build_transfer_host",
            "coarsen_transfer_host",
            "kernel_names", "SPDE_FP64", "SPDE_MIXED"]
 
@@ -149,20 +149,48 @@ def coarsen_transfer_host(n_fine: int, row_ptr, cols, vals):
     return row_ptr_c, cols_c, vals_c
 
 
-def transfer_row_order(row_ptr, cols, rows_first: bool = False):
-    """Row visiting order of the transfer SpMM (rows sorted by first cell).
-    rows_first: `cols` holds only each row's first column (one value per row,
-    read for the non-empty rows)."""
+def transfer_chunk_rows() -> int:
+    """Rows per chunk of the transfer SpMM's visiting order."""
+    return int(_abi.lib().spde_transfer_chunk_rows())
+
+
+def transfer_chunk_order(n: int, row_ptr, cols, rows_first: bool = False):
+    """Chunk visiting order of the transfer SpMM for a Pi whose columns are the
+    cells of the n^3 box (see spde_transfer_chunk_order).  rows_first: `cols`
+    holds only each row's first column (one value per row, read for the
+    non-empty rows)."""
     rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
     ci = np.ascontiguousarray(cols, dtype=np.int32)
-    order = np.empty(rp.size - 1, dtype=np.int32)
+    nrows = rp.size - 1
     if rows_first:
         # CSR with one entry per non-empty row: its first column
         ne = rp[1:] > rp[:-1]
-        ci = np.ascontiguousarray(ci[:order.size][ne], dtype=np.int32)
+        ci = np.ascontiguousarray(ci[:nrows][ne], dtype=np.int32)
         rp = np.concatenate([[0], np.cumsum(ne)]).astype(np.int64)
-    _abi.check(_abi.lib().spde_transfer_row_order(order.size, rp.ctypes.data, ci.ctypes.data, order.ctypes.data))
+    L = _abi.lib()
+    chunk = L.spde_transfer_chunk_rows()
+    order = np.empty((nrows + chunk - 1) // chunk, dtype=np.int32)
+    _abi.check(L.spde_transfer_chunk_order(int(n), nrows, rp.ctypes.data, ci.ctypes.data, order.ctypes.data))
     return order
+
+
+def csr_apply(row_ptr, cols, vals, x, n_rows: int, order=None):
+    """y[b] = A x[b] for the CSR matrix A (device tensors: row_ptr int64
+    [n_rows + 1], cols int32, vals float64) and x [B, n_cols] float64 on the
+    device; the library's transfer product (order: optional int32 chunk
+    visiting order, see transfer_chunk_order).  Returns y [B, n_rows]."""
+    torch = _torch()
+    B, n_cols = x.shape
+    _check_dev_f64(x, (B, n_cols), "x")
+    y = torch.empty((B, int(n_rows)), dtype=torch.float64, device=x.device)
+    L = _abi.lib()
+    nbytes = L.spde_csr_apply_work_bytes(int(n_cols), int(B))
+    work = torch.empty(max(1, nbytes), dtype=torch.uint8, device=x.device) if nbytes else None
+    with torch.cuda.device(x.device):
+        _abi.check(L.spde_csr_apply(int(n_rows), int(cols.numel()), _ptr(row_ptr), _ptr(cols), _ptr(vals),
+                                    int(n_cols), int(B), _ptr(x), _ptr(y), _ptr(order), _ptr(work), nbytes,
+                                    _stream_ptr(x.device)))
+    return y
 
 
 def restrict_noise(xi_f, n_fine: int):
@@ -258,22 +286,22 @@ class Box:
         rp = torch.as_tensor(row_ptr, dtype=torch.int64).to(d)
         ci = torch.as_tensor(cols, dtype=torch.int32).to(d)
         cv = torch.as_tensor(vals, dtype=torch.float64).to(d)
-        # the SpMM row order is computed on the host from the row pointers and
+        # the SpMM chunk order is computed on the host from the row pointers and
         # each row's first column
         if isinstance(row_ptr, torch.Tensor) or isinstance(cols, torch.Tensor):
             rp_h = rp.cpu().numpy()
             first = (ci[rp[:-1].clamp(max=max(ci.numel() - 1, 0))].cpu().numpy() if ci.numel()
                      else np.zeros(rp_h.size - 1, np.int32))
-            order = transfer_row_order(rp_h, first, rows_first=True)
+            order = transfer_chunk_order(self.n, rp_h, first, rows_first=True)
         else:
-            order = transfer_row_order(row_ptr, cols)
+            order = transfer_chunk_order(self.n, row_ptr, cols)
         od = torch.as_tensor(order).to(d)
         self._pi = (rp, ci, cv, od)
         self.n_tet = rp.numel() - 1
         self.nnz = ci.numel()
         L = _abi.lib()
         _abi.check(L.spde_set_transfer(self._hh.h, self.n_tet, self.nnz, _ptr(rp), _ptr(ci), _ptr(cv)))
-        _abi.check(L.spde_set_transfer_order(self._hh.h, _ptr(od)))
+        _abi.check(L.spde_set_transfer_chunk_order(self._hh.h, _ptr(od)))
         return self.n_tet, self.nnz
 
     # -- coefficients ------------------------------------------------------

@@ -69,9 +69,12 @@ SIGNATURES = {
     "spde_slots_step": (C.c_int, [_vp, C.c_int, C.c_int, _vp]),
     "spde_slots_poll": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "spde_slot_finish": (C.c_int, [_vp, C.c_int, _vp, _vp]),
-    "spde_csr_apply": (C.c_int, [C.c_int64, C.c_int64, _vp, _vp, _vp, C.c_int64, C.c_int, _vp, _vp, _vp, _vp]),
-    "spde_transfer_row_order": (C.c_int, [C.c_int64, _vp, _vp, _vp]),
-    "spde_set_transfer_order": (C.c_int, [_vp, _vp]),
+    "spde_csr_apply_work_bytes": (C.c_size_t, [C.c_int64, C.c_int]),
+    "spde_csr_apply": (C.c_int, [C.c_int64, C.c_int64, _vp, _vp, _vp, C.c_int64, C.c_int, _vp, _vp, _vp, _vp,
+                                 C.c_size_t, _vp]),
+    "spde_transfer_chunk_rows": (C.c_int, []),
+    "spde_transfer_chunk_order": (C.c_int, [C.c_int, C.c_int64, _vp, _vp, _vp]),
+    "spde_set_transfer_chunk_order": (C.c_int, [_vp, _vp]),
     "spde_free_host": (None, [_vp]),
     "spde_destroy": (None, [_vp]),
     "spde_last_error": (C.c_char_p, []),

@@ -54,7 +54,7 @@ spde_status fail(spde_status s, const char* fmt, ...) {
 
 const char* kKernelNames[KID_COUNT] = {
     "init", "mg_down_fine", "mg_down", "mg_coarse", "mg_up", "mg_up_fine",
-    "scalar", "operator", "output", "flux", "resid", "spmm", "restrict_noise"};
+    "scalar", "operator", "output", "flux", "resid", "spmm", "restrict_noise", "spmm_stage"};
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -68,6 +68,7 @@ struct LaunchRec {
   int level;         // multigrid level of a level kernel
   int s0, nslots;    // slots of the launch (nslots < 0: the whole batch)
   hipEvent_t e0, e1;
+  double bytes;      // algorithmic bytes of the whole launch, or < 0: per slot from slot_bytes
 };
 
 struct Ctx {
@@ -115,7 +116,7 @@ struct Ctx {
   const int64_t* rp = nullptr;
   const int32_t* ci = nullptr;
   const double* cv = nullptr;
-  const int32_t* order = nullptr;   // optional row visiting order of the SpMM
+  const int32_t* order = nullptr;   // optional chunk visiting order of the SpMM
   // execution
   bool use_graphs = true;
   int poll = 8;
@@ -246,10 +247,12 @@ struct Timed {
   Ctx* c;
   int kid, iter, level, s0, nslots;
   hipStream_t st;
+  double bytes;
   hipEvent_t e0 = nullptr;
   bool on = false;
-  Timed(Ctx* c_, int kid_, int iter_, hipStream_t st_, int level_ = 0, int s0_ = 0, int nslots_ = -1)
-      : c(c_), kid(kid_), iter(iter_), level(level_), s0(s0_), nslots(nslots_), st(st_) {
+  Timed(Ctx* c_, int kid_, int iter_, hipStream_t st_, int level_ = 0, int s0_ = 0, int nslots_ = -1,
+        double bytes_ = -1.0)
+      : c(c_), kid(kid_), iter(iter_), level(level_), s0(s0_), nslots(nslots_), st(st_), bytes(bytes_) {
     on = !c->capturing && (c->timing == 1 || (c->timing == 2 && kid == KID_OPERATOR));
     if (!on) return;
     e0 = next_event(c);
@@ -260,7 +263,7 @@ struct Timed {
     hipEvent_t e1 = next_event(c);
     if (e1) {
       hipEventRecord(e1, st);
-      c->recs.push_back({kid, iter, level, s0, nslots, e0, e1});
+      c->recs.push_back({kid, iter, level, s0, nslots, e0, e1, bytes});
     }
   }
 };
@@ -291,6 +294,8 @@ double slot_bytes(const Ctx* c, int kid, int level, int iter, int wmode_active) 
     case KID_MG_DOWN: { const double m = (double)c->lv[level].nc; return m * (sz + sz / 8.0); }
     case KID_MG_UP: { const double m = (double)c->lv[level].nc; return m * (sz + sz / 8.0 + sz); }
     case KID_MG_COARSE: return 2.0 * (double)c->lv[c->top].nc * sz;
+    // v_1 = [0; F]: the noise read (or drawn), three face arrays and the cell array written
+    case KID_INIT: return nc * 40.0;
     default: return 0.0;
   }
 }
@@ -487,8 +492,8 @@ void close_timing(Ctx* c, int batch) {
   for (const LaunchRec& r : c->recs) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) continue;
-    double bytes = 0.0;
-    const int s_end = r.nslots < 0 ? batch : std::min(batch, r.s0 + r.nslots);
+    double bytes = r.bytes >= 0.0 ? r.bytes : 0.0;
+    const int s_end = r.bytes >= 0.0 ? r.s0 : (r.nslots < 0 ? batch : std::min(batch, r.s0 + r.nslots));
     for (int s = r.s0; s < s_end; ++s) {
       const bool done = states[s] == ST_DONE || states[s] == ST_FINISH;
       const int J = done ? iters[s] : (1 << 30);
@@ -951,6 +956,29 @@ spde_status check_noise_grid(const Ctx* c, int coupled) {
   return SPDE_OK;
 }
 
+// u_tet = Pi u for a batch of box fields, the samples staged sample-minor in
+// the second Lanczos face buffer (free between solves; 3 batch n^3 doubles
+// hold any sample block), with the algorithmic bytes of each launch:
+// staging reads the block's fields and writes the staged block, the gather
+// reads the CSR once per sample block, the staged fields and writes u_tet.
+spde_status enqueue_transfer(Ctx* c, int batch, const double* u, double* u_tet, hipStream_t st) {
+  const int bp = spmm_block(batch);
+  const double nc = (double)c->box.nc, nt = (double)c->n_tet;
+  const double csr = 8.0 * (nt + 1.0) + 12.0 * (double)c->nnz;
+  double* scratch = c->F.vs[1];
+  for (int s0 = 0; s0 < batch; s0 += bp) {
+    const int nb = std::min(bp, batch - s0);
+    if (bp > 1) {
+      Timed t(c, KID_SPMM_STAGE, 0, st, 0, s0, nb, 8.0 * nc * (nb + bp));
+      HIPCHK(launch_spmm_stage(u, scratch, c->box.nc, batch, s0, st));
+    }
+    Timed t(c, KID_SPMM, 0, st, 0, s0, nb, csr + 8.0 * nb * (nc + nt));
+    HIPCHK(launch_spmm_gather(c->rp, c->ci, c->cv, u, scratch, u_tet, c->n_tet, c->nnz, c->box.nc, batch, s0,
+                              c->order, st));
+  }
+  return SPDE_OK;
+}
+
 spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_dev, double* u_box_dev,
                         double* sigma_dev, void* stream, int* iters_host, double* relres_host,
                         const double* warm_uc = nullptr) {
@@ -1156,8 +1184,8 @@ spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_de
     }
   }
   if (u_tet_dev) {
-    Timed t(c, KID_SPMM, 0, st);
-    HIPCHK(launch_spmm(c->rp, c->ci, c->cv, c->F.x, u_tet_dev, c->n_tet, c->nnz, bx.nc, batch, c->order, st));
+    s = enqueue_transfer(c, batch, c->F.x, u_tet_dev, st);
+    if (s != SPDE_OK) return s;
   }
   if (relres_host || c->timing) {
     HIPCHK(hipStreamSynchronize(st));
@@ -1347,12 +1375,23 @@ spde_status spde_slot_finish(spde_handle h, int slot, double* u_box_dev, void* s
   return SPDE_OK;
 }
 
+size_t spde_csr_apply_work_bytes(int64_t n_cols, int batch) {
+  if (n_cols < 1 || batch < 1) return 0;
+  return spmm_scratch_bytes(n_cols, batch);
+}
+
 spde_status spde_csr_apply(int64_t n_rows, int64_t nnz, const int64_t* rp, const int32_t* ci, const double* cv,
                            int64_t n_cols, int batch, const double* x_dev, double* y_dev,
-                           const int32_t* order_dev, void* stream) {
+                           const int32_t* chunk_order_dev, void* work_dev, size_t work_bytes, void* stream) {
   if (n_rows < 1 || nnz < 0 || n_cols < 1 || batch < 1) return fail(SPDE_EINVAL, "invalid sizes");
   if (!rp || !x_dev || !y_dev || (nnz > 0 && (!ci || !cv))) return fail(SPDE_EINVAL, "null pointer");
-  HIPCHK(launch_spmm(rp, ci, cv, x_dev, y_dev, n_rows, nnz, n_cols, batch, order_dev, (hipStream_t)stream));
+  const size_t need = spmm_scratch_bytes(n_cols, batch);
+  if (need && (!work_dev || work_bytes < need))
+    return fail(SPDE_EINVAL, "work buffer has %zu bytes, %zu needed for batch %d", work_dev ? work_bytes : 0, need,
+                batch);
+  if (need && ((uintptr_t)work_dev & 255)) return fail(SPDE_EINVAL, "work buffer must be 256-byte aligned");
+  HIPCHK(launch_spmm(rp, ci, cv, x_dev, y_dev, n_rows, nnz, n_cols, batch, chunk_order_dev, (double*)work_dev,
+                     (hipStream_t)stream));
   return SPDE_OK;
 }
 
@@ -1424,29 +1463,47 @@ spde_status spde_apply_vcycle(spde_handle h, int batch, const double* r_dev, dou
 
 spde_status spde_apply_transfer(spde_handle h, int batch, const double* u_box_dev, double* u_tet_dev, void* stream) {
   Ctx* c = reinterpret_cast<Ctx*>(h);
-  if (!c) return fail(SPDE_EINVAL, "null handle");
+  spde_status s = check_ready(c);
+  if (s != SPDE_OK) return s;
   if (!c->rp) return fail(SPDE_EINVAL, "no transfer set");
-  if (batch < 1 || !u_box_dev || !u_tet_dev) return fail(SPDE_EINVAL, "invalid argument");
-  if (c->device >= 0) HIPCHK(hipSetDevice(c->device));
-  HIPCHK(launch_spmm(c->rp, c->ci, c->cv, u_box_dev, u_tet_dev, c->n_tet, c->nnz, c->box.nc, batch, c->order,
-                     (hipStream_t)stream));
-  return SPDE_OK;
+  if (batch < 1 || batch > c->max_batch || !u_box_dev || !u_tet_dev) return fail(SPDE_EINVAL, "invalid argument");
+  HIPCHK(hipSetDevice(c->device));
+  return enqueue_transfer(c, batch, u_box_dev, u_tet_dev, pick_stream(c, stream));
 }
 
-spde_status spde_transfer_row_order(int64_t n_rows, const int64_t* row_ptr_host, const int32_t* col_host,
-                                    int32_t* order_host) {
-  if (n_rows < 1 || n_rows > INT32_MAX || !row_ptr_host || !order_host) return fail(SPDE_EINVAL, "invalid argument");
-  std::vector<std::pair<int64_t, int32_t>> key(n_rows);
-  for (int64_t r = 0; r < n_rows; ++r) {
-    const int64_t k0 = row_ptr_host[r], k1 = row_ptr_host[r + 1];
-    key[r] = {(k1 > k0 && col_host) ? (int64_t)col_host[k0] : INT64_MAX, (int32_t)r};
+int spde_transfer_chunk_rows(void) { return kSpmmChunk; }
+
+spde_status spde_transfer_chunk_order(int n, int64_t n_rows, const int64_t* row_ptr_host, const int32_t* col_host,
+                                      int32_t* order_host) {
+  if (n < 1 || n > 1024) return fail(SPDE_EINVAL, "n must lie in [1, 1024]");
+  if (n_rows < 1 || !row_ptr_host || !order_host) return fail(SPDE_EINVAL, "invalid argument");
+  const int64_t nchunk = (n_rows + kSpmmChunk - 1) / kSpmmChunk;
+  if (nchunk > INT32_MAX) return fail(SPDE_EINVAL, "too many rows");
+  // key of a chunk: the cell of its first entry, ordered by 16 x 16 tile of
+  // (x, y), then z, then y, then x; chunks without entries last
+  const int64_t tiles = (n + 15) / 16;
+  std::vector<std::pair<uint64_t, int32_t>> key(nchunk);
+  for (int64_t q = 0; q < nchunk; ++q) {
+    uint64_t k = UINT64_MAX;
+    const int64_t r1 = std::min(n_rows, (q + 1) * kSpmmChunk);
+    for (int64_t r = q * kSpmmChunk; r < r1 && col_host; ++r) {
+      if (row_ptr_host[r + 1] > row_ptr_host[r]) {
+        const int64_t c = col_host[row_ptr_host[r]];
+        if (c < 0 || c >= (int64_t)n * n * n) break;
+        const uint64_t i = c % n, j = (c / n) % n, kz = c / ((int64_t)n * n);
+        const uint64_t tile = (i / 16) * tiles + j / 16;
+        k = (tile << 30) | (kz << 20) | (j << 10) | i;
+        break;
+      }
+    }
+    key[q] = {k, (int32_t)q};
   }
   std::stable_sort(key.begin(), key.end());
-  for (int64_t r = 0; r < n_rows; ++r) order_host[r] = key[r].second;
+  for (int64_t q = 0; q < nchunk; ++q) order_host[q] = key[q].second;
   return SPDE_OK;
 }
 
-spde_status spde_set_transfer_order(spde_handle h, const int32_t* order_dev) {
+spde_status spde_set_transfer_chunk_order(spde_handle h, const int32_t* order_dev) {
   Ctx* c = reinterpret_cast<Ctx*>(h);
   if (!c) return fail(SPDE_EINVAL, "null handle");
   if (!c->rp) return fail(SPDE_EINVAL, "no transfer set");

@@ -148,7 +148,7 @@ __host__ __device__ inline int64_t face_off(int slot, int d, int64_t nc) { retur
 // Kernel classes (for timing and names).
 enum KernelId : int {
   KID_INIT = 0, KID_MG_DOWN_FINE, KID_MG_DOWN, KID_MG_COARSE, KID_MG_UP, KID_MG_UP_FINE,
-  KID_SCALAR, KID_OPERATOR, KID_OUTPUT, KID_FLUX, KID_RESID, KID_SPMM, KID_RESTRICT,
+  KID_SCALAR, KID_OPERATOR, KID_OUTPUT, KID_FLUX, KID_RESID, KID_SPMM, KID_RESTRICT, KID_SPMM_STAGE,
   KID_COUNT
 };
 
@@ -216,8 +216,20 @@ hipError_t launch_inject_coarse(const double* uc, double* x, int n, int batch, h
 // The tolerance of slot b is tols[b] (device array [batch]).
 hipError_t launch_init_correction(const Fields& F, const Box& bx, int batch, const double* tols, int max_iter,
                                   hipStream_t st);
+// Transfer SpMM out[s][row] = (Pi u[s])[row]: samples in blocks of
+// spmm_block(batch), each staged sample-minor into `scratch`
+// (spmm_scratch_bytes(nc, batch) bytes; unused for batch 1), then gathered,
+// rows in chunks of kSpmmChunk visited in the chunk order corder (nullable).
+constexpr int kSpmmChunk = 64;
+int spmm_block(int batch);
+size_t spmm_scratch_bytes(int64_t nc, int batch);
+hipError_t launch_spmm_stage(const double* u, double* xt, int64_t nc, int batch, int s0, hipStream_t st);
+hipError_t launch_spmm_gather(const int64_t* rp, const int32_t* ci, const double* cv, const double* u,
+                              const double* xt, double* out, int64_t ntet, int64_t nnz, int64_t nc, int batch,
+                              int s0, const int32_t* corder, hipStream_t st);
 hipError_t launch_spmm(const int64_t* rp, const int32_t* ci, const double* cv, const double* u, double* out,
-                       int64_t ntet, int64_t nnz, int64_t nc, int batch, const int32_t* order, hipStream_t st);
+                       int64_t ntet, int64_t nnz, int64_t nc, int batch, const int32_t* corder, double* scratch,
+                       hipStream_t st);
 hipError_t launch_restrict_noise(const double* xf, double* xc, int nf, int batch, hipStream_t st);
 hipError_t launch_ext_to_int(const double* xs, const double* xu, const Fields& F, const Box& bx, int batch,
                              hipStream_t st);

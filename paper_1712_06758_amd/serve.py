@@ -141,12 +141,12 @@ class GpuEngine:
 
     def add_transfer(self, name, rp, ci, cv):
         """Register a host CSR Pi of this box onto the tet mesh `name`."""
-        from . import transfer_row_order
+        from . import transfer_chunk_order
         torch = self.torch
         d = self.device
         self.transfers[name] = (rp.size - 1, ci.size, torch.as_tensor(rp).to(d),
                                 torch.as_tensor(ci).to(d), torch.as_tensor(cv).to(d),
-                                torch.as_tensor(transfer_row_order(rp, ci)).to(d))
+                                torch.as_tensor(transfer_chunk_order(self.n, rp, ci)).to(d))
 
     def has_free(self):
         return bool(self.free)
@@ -205,9 +205,11 @@ class GpuEngine:
             u = torch.empty(self.n ** 3, dtype=torch.float64, device=self.device)
             ut = torch.empty(n_tet, dtype=torch.float64, device=self.device)
             _abi.check(L.spde_slot_finish(self.box._hh.h, part.slot, C.c_void_p(u.data_ptr()), self._sp()))
+            # one sample: the product needs no work buffer
             _abi.check(L.spde_csr_apply(n_tet, nnz, C.c_void_p(rp.data_ptr()), C.c_void_p(ci.data_ptr()),
                                         C.c_void_p(cv.data_ptr()), self.n ** 3, 1, C.c_void_p(u.data_ptr()),
-                                        C.c_void_p(ut.data_ptr()), C.c_void_p(od.data_ptr()), self._sp()))
+                                        C.c_void_p(ut.data_ptr()), C.c_void_p(od.data_ptr()), None, 0,
+                                        self._sp()))
             part.done_event = torch.cuda.Event()
             part.done_event.record(self.stream)
         del self.busy[part.slot]

@@ -274,3 +274,21 @@ def test_stream_create_cu_mask_validation(lib):
     assert L.spde_stream_create_cu_mask(8, None, C.byref(out)) == -1
     assert L.spde_stream_create_cu_mask(8, w.ctypes.data, None) == -1
     assert L.spde_stream_destroy(None) == -1
+
+
+def test_csr_apply_validates_before_launching(lib):
+    """Sizes, null arrays and the work buffer are checked on the host."""
+    from paper_1712_06758_amd import _abi
+    L = _abi.lib()
+    buf = C.c_void_p(0x1000)           # never dereferenced: every call below fails validation first
+    assert L.spde_csr_apply_work_bytes(0, 4) == 0
+    assert L.spde_csr_apply_work_bytes(100, 1) == 0                  # one sample needs no staging
+    assert L.spde_csr_apply_work_bytes(100, 3) == 4 * 100 * 8        # staged as a power-of-two block
+    assert L.spde_csr_apply_work_bytes(100, 64) == 64 * 100 * 8
+    assert L.spde_csr_apply_work_bytes(100, 200) == 64 * 100 * 8     # blocks of 64 reuse the buffer
+    assert L.spde_csr_apply(0, 0, buf, buf, buf, 10, 1, buf, buf, None, None, 0, None) == -1
+    assert L.spde_csr_apply(5, 9, None, buf, buf, 10, 1, buf, buf, None, None, 0, None) == -1
+    assert L.spde_csr_apply(5, 9, buf, buf, buf, 10, 2, buf, buf, None, None, 0, None) == -1   # no work buffer
+    assert b"needed" in L.spde_last_error()
+    assert L.spde_csr_apply(5, 9, buf, buf, buf, 10, 2, buf, buf, None, buf, 100, None) == -1  # too small
+    assert L.spde_csr_apply(5, 9, buf, buf, buf, 10, 2, buf, buf, None, C.c_void_p(0x1008), 4096, None) == -1
