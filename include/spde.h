@@ -350,6 +350,25 @@ spde_status spde_csr_apply(int64_t n_rows, int64_t nnz, const int64_t* row_ptr_d
                            const int32_t* chunk_order_dev /* nullable */, void* work_dev,
                            size_t work_bytes, void* stream);
 
+/* The same product without a work buffer, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the staged sample block lives in a device array
+ * of the library, spde_csr_apply_noalloc_max_bytes() = 64 MiB, that each GPU
+ * holds from the call's first use on it until the process ends.  The call
+ * allocates nothing; it accepts the sizes whose staged block fits that array
+ * (spde_csr_apply_work_bytes(n_cols, batch) <= 64 MiB, e.g. 64 samples of a
+ * 32^3 box or 32 of a 64^3 box; batch 1 always) and returns SPDE_EINVAL with
+ * the sizes for larger ones.  Arguments, results (bitwise those of
+ * spde_csr_apply) and other errors as spde_csr_apply.  All calls on one GPU
+ * share the array: calls that overlap on that GPU (other streams or host
+ * threads) race and must be serialised by the caller.  Asynchronous on
+ * `stream`. */
+size_t spde_csr_apply_noalloc_max_bytes(void);
+spde_status spde_csr_apply_noalloc(int64_t n_rows, int64_t nnz, const int64_t* row_ptr_dev,
+                                   const int32_t* col_dev, const double* val_dev, int64_t n_cols,
+                                   int batch, const double* x_dev, double* y_dev,
+                                   const int32_t* chunk_order_dev /* nullable */, void* stream);
+
 /* ---- operators exposed for verification -------------------------------- */
 
 /* y = A x with A the saddle-point matrix of eq. linsys_blocks on the full

@@ -70,6 +70,9 @@ SIGNATURES = {
     "spde_slots_poll": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "spde_slot_finish": (C.c_int, [_vp, C.c_int, _vp, _vp]),
     "spde_csr_apply_work_bytes": (C.c_size_t, [C.c_int64, C.c_int]),
+    "spde_csr_apply_noalloc_max_bytes": (C.c_size_t, []),
+    "spde_csr_apply_noalloc": (C.c_int, [C.c_int64, C.c_int64, _vp, _vp, _vp, C.c_int64, C.c_int, _vp, _vp, _vp,
+                                         _vp]),
     "spde_csr_apply": (C.c_int, [C.c_int64, C.c_int64, _vp, _vp, _vp, C.c_int64, C.c_int, _vp, _vp, _vp, _vp,
                                  C.c_size_t, _vp]),
     "spde_transfer_chunk_rows": (C.c_int, []),

@@ -1395,6 +1395,26 @@ spde_status spde_csr_apply(int64_t n_rows, int64_t nnz, const int64_t* rp, const
   return SPDE_OK;
 }
 
+spde_status spde_csr_apply_noalloc(int64_t n_rows, int64_t nnz, const int64_t* rp, const int32_t* ci,
+                                   const double* cv, int64_t n_cols, int batch, const double* x_dev, double* y_dev,
+                                   const int32_t* chunk_order_dev, void* stream) {
+  if (n_rows < 1 || nnz < 0 || n_cols < 1 || batch < 1) return fail(SPDE_EINVAL, "invalid sizes");
+  if (!rp || !x_dev || !y_dev || (nnz > 0 && (!ci || !cv))) return fail(SPDE_EINVAL, "null pointer");
+  const size_t need = spmm_scratch_bytes(n_cols, batch);
+  if (need > kStaticScratchBytes)
+    return fail(SPDE_EINVAL,
+                "the staged sample block needs %zu bytes (%d samples x %lld columns), the static scratch holds %zu; "
+                "use spde_csr_apply with a work buffer", need, spmm_block(batch), (long long)n_cols,
+                kStaticScratchBytes);
+  double* scratch_dev = nullptr;
+  if (need) HIPCHK(static_scratch_ptr(&scratch_dev));
+  HIPCHK(launch_spmm(rp, ci, cv, x_dev, y_dev, n_rows, nnz, n_cols, batch, chunk_order_dev, scratch_dev,
+                     (hipStream_t)stream));
+  return SPDE_OK;
+}
+
+size_t spde_csr_apply_noalloc_max_bytes(void) { return kStaticScratchBytes; }
+
 spde_status spde_restrict_noise(int n_fine, int batch, const double* xi_f_dev, double* xi_c_dev, void* stream) {
   if (n_fine < 2 || (n_fine & 1)) return fail(SPDE_EINVAL, "n_fine must be even and >= 2");
   if (batch < 1) return fail(SPDE_EINVAL, "batch must be >= 1");

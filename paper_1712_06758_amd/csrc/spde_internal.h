@@ -221,6 +221,10 @@ hipError_t launch_init_correction(const Fields& F, const Box& bx, int batch, con
 // (spmm_scratch_bytes(nc, batch) bytes; unused for batch 1), then gathered,
 // rows in chunks of kSpmmChunk visited in the chunk order corder (nullable).
 constexpr int kSpmmChunk = 64;
+// Static device scratch of the no-allocation transfer product (per device).
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch_ptr(double** out);
 int spmm_block(int batch);
 size_t spmm_scratch_bytes(int64_t nc, int batch);
 hipError_t launch_spmm_stage(const double* u, double* xt, int64_t nc, int batch, int s0, hipStream_t st);

@@ -19,6 +19,8 @@
 //                                      convergence test
 //   operator                         : v_{j+1} = A z_j - (delta/gamma) v_j - (gamma/gamma_prev) v_{j-1}
 //                                      and the delayed w/x update of step j-1
+#include <mutex>
+
 #include "spde_common.inc"
 
 namespace spde {
