@@ -294,8 +294,6 @@ double slot_bytes(const Ctx* c, int kid, int level, int iter, int wmode_active) 
     case KID_MG_DOWN: { const double m = (double)c->lv[level].nc; return m * (sz + sz / 8.0); }
     case KID_MG_UP: { const double m = (double)c->lv[level].nc; return m * (sz + sz / 8.0 + sz); }
     case KID_MG_COARSE: return 2.0 * (double)c->lv[c->top].nc * sz;
-    // v_1 = [0; F]: the noise read (or drawn), three face arrays and the cell array written
-    case KID_INIT: return nc * 40.0;
     default: return 0.0;
   }
 }
@@ -1025,7 +1023,8 @@ spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_de
     return SPDE_OK;
   };
   if (!warm_uc) {
-    Timed t(c, KID_INIT, 0, st);
+    // the noise read (none when drawn), three face arrays and the cell array written
+    Timed t(c, KID_INIT, 0, st, 0, 0, batch, (src.xi ? 40.0 : 32.0) * (double)bx.nc * batch);
     if (src.xi) HIPCHK(launch_init(c->F, bx, src.xi, scale, batch, c->rtol, c->max_iter, 0, st));
     else
       HIPCHK(launch_init_gen(c->F, bx, src.seed, src.event0, src.coupled, scale, batch, c->rtol, c->max_iter, 0,
@@ -1043,7 +1042,8 @@ spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_de
       c->host_res[b] = std::isfinite(r0) && r0 > 0.0 ? std::min(0.5, std::max(c->rtol, c->rtol / r0)) : c->rtol;
     }
     HIPCHK(hipMemcpyAsync(c->resid_out, c->host_res, batch * sizeof(double), hipMemcpyHostToDevice, st));
-    Timed t(c, KID_INIT, 0, st);
+    // three face arrays of v_1 cleared (the cell part was written by the residual pass)
+    Timed t(c, KID_INIT, 0, st, 0, 0, batch, 24.0 * (double)bx.nc * batch);
     HIPCHK(launch_init_correction(c->F, bx, batch, c->resid_out, c->max_iter, st));
   }
   const bool graphs = c->use_graphs && c->timing != 1 && st != nullptr;

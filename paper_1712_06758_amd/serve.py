@@ -384,6 +384,9 @@ class Server:
                                 "mean_queue_wait_ms": round(1e3 * float(np.mean(wait)), 3),
                                 "mean_iters": round(float(np.mean(it)), 2),
                                 "requests_per_s": round(len(reqs) / wall, 2) if wall > 0 else 0.0}
+        # a request is one coupled pair (fine + coarse part, fine only on the
+        # coarsest level); samples count the parts
+        out["requests_per_s"] = round(len(done) / wall, 2) if wall > 0 else 0.0
         out["samples_per_s"] = round(samples / wall, 2) if wall > 0 else 0.0
         out["max_queue_depth"] = max((d for _, d in self.queue_depth), default=0)
         return out
