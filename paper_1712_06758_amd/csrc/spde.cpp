@@ -182,7 +182,7 @@ void plan_hierarchy(Ctx* c) {
   // persistent kernel: the largest levels (below the finest) that fit in LDS, at most 16^3
   int top = c->nlev - 1;
   for (int l = 1; l < c->nlev; ++l) {
-    if (c->lv[l].m <= 16 && coarse_bytes(c, l) <= (size_t)c->lds_limit) { top = l; break; }
+    if (c->lv[l].m <= 16 && coarse_bytes(c, l) + kCoarseStaticLds <= (size_t)c->lds_limit) { top = l; break; }
   }
   c->top = top;
   c->coarse_lds = coarse_bytes(c, top);

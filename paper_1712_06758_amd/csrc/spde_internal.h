@@ -14,6 +14,8 @@
 namespace spde {
 
 constexpr int kMaxLevels = 12;
+// static LDS of the persistent coarse kernel (a table of 8 reciprocals per level)
+constexpr size_t kCoarseStaticLds = kMaxLevels * 8 * sizeof(double);
 constexpr int kBlock = 256;          // threads per block of the streaming kernels
 
 // Per-sample solver state (one per batch slot).

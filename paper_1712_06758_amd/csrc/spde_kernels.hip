@@ -446,14 +446,18 @@ __global__ __launch_bounds__(kBlock, WPS) void k_spmm_gather(const int64_t* __re
 // The same product for blocks of BP <= 8 samples: one row per lane, its BP
 // samples contiguous in xt (one load of BP x 8 bytes per entry), a wave on the
 // 64 rows of one chunk, so that the entries it reads and the values it stores
-// are contiguous.  For BP = 1 xt is the sample's own field.
+// are contiguous.  For BP = 1 xt is the sample's own field.  A row's entries
+// are taken U at a time: their columns and values are all loaded before the
+// gathers, and the gathers before the sums, so that a lane has U loads in
+// flight; the sums keep the entry order.
 template <int BP>
 __global__ __launch_bounds__(kBlock) void k_spmm_rows(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                       const double* __restrict__ cv, const double* __restrict__ xt,
-                                                      double* __restrict__ out, int64_t ntet, int64_t nnz,
-                                                      int64_t nc, int batch, int s0,
+                                                      double* __restrict__ out, int64_t ntet, int64_t nnz, int64_t nc,
+                                                      int batch, int s0,
                                                       const int32_t* __restrict__ corder, int64_t nchunk) {
   static_assert(BP >= 1 && BP <= 8 && kSpmmChunk == 64, "sample block; a wave per chunk");
+  constexpr int U = BP >= 8 ? 2 : 16 / BP;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t q = (int64_t)lb * (kBlock / 64) + (threadIdx.x >> 6);
   if (q >= nchunk) return;
@@ -464,14 +468,29 @@ __global__ __launch_bounds__(kBlock) void k_spmm_rows(const int64_t* __restrict_
   double acc[BP];
 #pragma unroll
   for (int q2 = 0; q2 < BP; ++q2) acc[q2] = 0.0;
-#pragma unroll 4
-  for (int64_t k = k0; k < k1; ++k) {
-    const int64_t col = ci[k];
-    const double v = cv[k];
-    if (col < 0 || col >= nc) continue;
-    const double* px = xt + col * BP;
+  for (int64_t k = k0; k < k1; k += U) {
+    int64_t col[U];
+    double v[U];
 #pragma unroll
-    for (int q2 = 0; q2 < BP; ++q2) acc[q2] += v * px[q2];
+    for (int u = 0; u < U; ++u) {
+      const bool in = k + u < k1;
+      col[u] = in ? (int64_t)ci[k + u] : -1;
+      v[u] = in ? cv[k + u] : 0.0;
+    }
+    double xv[U][BP];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double* px = xt + ((col[u] >= 0 && col[u] < nc) ? col[u] : 0) * BP;
+#pragma unroll
+      for (int q2 = 0; q2 < BP; ++q2) xv[u][q2] = px[q2];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (col[u] >= 0 && col[u] < nc) {
+#pragma unroll
+        for (int q2 = 0; q2 < BP; ++q2) acc[q2] += v[u] * xv[u][q2];
+      }
+    }
   }
 #pragma unroll
   for (int q2 = 0; q2 < BP; ++q2)
