@@ -174,6 +174,39 @@ spde_status spde_transfer_chunk_order(int n, int64_t n_rows, const int64_t* row_
  * wherever it runs. */
 spde_status spde_set_transfer_chunk_order(spde_handle h, const int32_t* order_dev);
 
+/* Row units of the LDS-staged transfer product (eq. proj_op, u_tet = Pi u).
+ * The rows are grouped in units of spde_transfer_unit_rows() consecutive rows
+ * (a chunk holds a whole number of units).  For each unit: the distinct box
+ * cells its entries reference, ascending, and for each entry the index of its
+ * column in that list.  The product then loads each unit's cells once into
+ * LDS and forms all of the unit's rows from there.
+ *   row_ptr_host  [n_rows + 1] int64, col_host [nnz] int32: Pi as built above
+ *   unit_ptr_host [n_units + 1] int64 out, n_units = ceil(n_rows / unit rows):
+ *                 offsets of each unit's list in unit_cells_host
+ *   unit_cells_host [unit_ptr_host[n_units]] int32 out (NULL: first call)
+ *   local_col_host  [nnz] uint16 out (NULL: first call); 65535 for a column
+ *                 outside [0, n_cols) (the product skips it, as spde_csr_apply)
+ *   max_cells, max_entries out: the largest count of cells / entries of a unit
+ * Two calls: the first (both list pointers NULL) writes unit_ptr_host and the
+ * maxima, the second fills the lists.  Host arrays, caller-owned; no device
+ * call.  SPDE_EINVAL for null pointers, n_rows < 1, n_cols < 1 or row pointers
+ * that decrease or leave [0, nnz]. */
+int spde_transfer_unit_rows(void);
+spde_status spde_transfer_units(int64_t n_rows, int64_t n_cols, const int64_t* row_ptr_host,
+                                const int32_t* col_host, int64_t* unit_ptr_host, int32_t* unit_cells_host,
+                                uint16_t* local_col_host, int32_t* max_cells, int32_t* max_entries);
+
+/* Register device copies of spde_transfer_units' lists for the handle's
+ * transfer (borrowed: they must stay valid while the handle samples; they must
+ * come from the registered matrix).  The transfer product of the sampling
+ * calls then uses the LDS-staged kernel for sample blocks of 32 or 64 samples
+ * whose largest unit fits its LDS budget (60 KiB per block), and the chunked
+ * gather otherwise.  Results are bitwise those of the gather: each row's sum
+ * runs over its entries in the same order.  spde_set_transfer clears the
+ * registration; NULL pointers clear it too. */
+spde_status spde_set_transfer_units(spde_handle h, const int64_t* unit_ptr_dev, const int32_t* unit_cells_dev,
+                                    const uint16_t* local_col_dev, int32_t max_cells, int32_t max_entries);
+
 /* ---- the sampler --------------------------------------------------------- */
 
 /* Draw `batch` field samples from the noise vectors xi_dev [batch][n^3]:
@@ -462,7 +495,9 @@ spde_status spde_stream_destroy(void* stream);
  * SPDE_TUNE_CACHE (if set), from which later processes read it; with
  * SPDE_TUNE_VERBOSE=1 every timed shape is printed to stderr.  Off: fixed
  * default tiles.  Results depend on the tiles only through the rounding of
- * per-block partial sums (a few ulps). */
+ * per-block partial sums (a few ulps): with the same tiles (spde_get_tiles after
+ * a call, spde_set_tiles in another handle or process, or a shared
+ * SPDE_TUNE_CACHE) a seeded sample is reproduced bit for bit. */
 spde_status spde_set_autotune(spde_handle h, int enable);
 
 /* Tile shape ids of the per-level multigrid kernels (level 0 = finest):

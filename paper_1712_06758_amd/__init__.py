@@ -174,6 +174,26 @@ def transfer_chunk_order(n: int, row_ptr, cols, rows_first: bool = False):
     return order
 
 
+def transfer_units(row_ptr, cols, n_cols: int):
+    """Row units of the LDS-staged transfer product (see spde_transfer_units):
+    (unit_ptr int64 [n_units + 1], unit_cells int32, local_col uint16 [nnz],
+    max_cells, max_entries) for the CSR matrix (host arrays)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(cols, dtype=np.int32)
+    nrows = rp.size - 1
+    L = _abi.lib()
+    nunit = (nrows + L.spde_transfer_unit_rows() - 1) // L.spde_transfer_unit_rows()
+    uptr = np.empty(nunit + 1, dtype=np.int64)
+    mc = C.c_int32(); me = C.c_int32()
+    _abi.check(L.spde_transfer_units(nrows, int(n_cols), rp.ctypes.data, ci.ctypes.data, uptr.ctypes.data, None, None,
+                                     C.byref(mc), C.byref(me)))
+    cells = np.empty(max(1, int(uptr[-1])), dtype=np.int32)
+    lcol = np.empty(max(1, ci.size), dtype=np.uint16)
+    _abi.check(L.spde_transfer_units(nrows, int(n_cols), rp.ctypes.data, ci.ctypes.data, uptr.ctypes.data,
+                                     cells.ctypes.data, lcol.ctypes.data, C.byref(mc), C.byref(me)))
+    return uptr, cells[: int(uptr[-1])], lcol[: ci.size], mc.value, me.value
+
+
 def csr_apply(row_ptr, cols, vals, x, n_rows: int, order=None):
     """y[b] = A x[b] for the CSR matrix A (device tensors: row_ptr int64
     [n_rows + 1], cols int32, vals float64) and x [B, n_cols] float64 on the
@@ -286,22 +306,24 @@ class Box:
         rp = torch.as_tensor(row_ptr, dtype=torch.int64).to(d)
         ci = torch.as_tensor(cols, dtype=torch.int32).to(d)
         cv = torch.as_tensor(vals, dtype=torch.float64).to(d)
-        # the SpMM chunk order is computed on the host from the row pointers and
-        # each row's first column
+        # the SpMM chunk order and row units are computed on the host from the
+        # row pointers and columns
         if isinstance(row_ptr, torch.Tensor) or isinstance(cols, torch.Tensor):
-            rp_h = rp.cpu().numpy()
-            first = (ci[rp[:-1].clamp(max=max(ci.numel() - 1, 0))].cpu().numpy() if ci.numel()
-                     else np.zeros(rp_h.size - 1, np.int32))
-            order = transfer_chunk_order(self.n, rp_h, first, rows_first=True)
+            rp_h, ci_h = rp.cpu().numpy(), ci.cpu().numpy()
         else:
-            order = transfer_chunk_order(self.n, row_ptr, cols)
+            rp_h, ci_h = np.asarray(row_ptr), np.asarray(cols)
+        order = transfer_chunk_order(self.n, rp_h, ci_h)
+        uptr, ucells, lcol, mc, me = transfer_units(rp_h, ci_h, self.n ** 3)
         od = torch.as_tensor(order).to(d)
-        self._pi = (rp, ci, cv, od)
+        units = (torch.as_tensor(uptr).to(d), torch.as_tensor(ucells).to(d),
+                 torch.from_numpy(lcol.view(np.int16)).to(d))
+        self._pi = (rp, ci, cv, od) + units
         self.n_tet = rp.numel() - 1
         self.nnz = ci.numel()
         L = _abi.lib()
         _abi.check(L.spde_set_transfer(self._hh.h, self.n_tet, self.nnz, _ptr(rp), _ptr(ci), _ptr(cv)))
         _abi.check(L.spde_set_transfer_chunk_order(self._hh.h, _ptr(od)))
+        _abi.check(L.spde_set_transfer_units(self._hh.h, _ptr(units[0]), _ptr(units[1]), _ptr(units[2]), mc, me))
         return self.n_tet, self.nnz
 
     # -- coefficients ------------------------------------------------------
@@ -339,7 +361,8 @@ class Box:
 
         Returns a dict with "u_tet" [B, n_tet] (if a mesh is set and u_tet),
         "u_box" [B, n^3], "sigma" [B, 3 n^2 (n+1)], "iters" (numpy int32 [B]),
-        "relres" (numpy float64 [B]) and "status".  allow_notconv /
+        "relres" (numpy float64 [B]), "status" and "tiles" (the multigrid tile
+        shapes (down, up) per level that the call ran with).  allow_notconv /
         allow_failed return the outputs with SPDE_ENOTCONV / SPDE_EFAILED
         instead of raising (a failed sample's fields are NaN, the others are
         valid)."""
@@ -396,6 +419,10 @@ class Box:
         out["iters"] = iters
         if rel is not None:
             out["relres"] = rel
+        # the multigrid tile shapes the call ran with: the results depend on them
+        # through the rounding of per-block partial sums, so a handle with these
+        # shapes fixed (set_tiles per level) reproduces the call bit for bit
+        out["tiles"] = self.info()["tiles"]
         return out
 
     # -- operators exposed for verification ------------------------------

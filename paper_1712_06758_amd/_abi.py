@@ -78,6 +78,9 @@ SIGNATURES = {
     "spde_transfer_chunk_rows": (C.c_int, []),
     "spde_transfer_chunk_order": (C.c_int, [C.c_int, C.c_int64, _vp, _vp, _vp]),
     "spde_set_transfer_chunk_order": (C.c_int, [_vp, _vp]),
+    "spde_transfer_unit_rows": (C.c_int, []),
+    "spde_transfer_units": (C.c_int, [C.c_int64, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "spde_set_transfer_units": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int32, C.c_int32]),
     "spde_free_host": (None, [_vp]),
     "spde_destroy": (None, [_vp]),
     "spde_last_error": (C.c_char_p, []),

@@ -15,6 +15,7 @@
 #include <functional>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/spde.h"
@@ -117,6 +118,12 @@ struct Ctx {
   const int32_t* ci = nullptr;
   const double* cv = nullptr;
   const int32_t* order = nullptr;   // optional chunk visiting order of the SpMM
+  // optional row units of the LDS-staged SpMM (spde_set_transfer_units)
+  const int64_t* uptr = nullptr;
+  const int32_t* ucells = nullptr;
+  const uint16_t* lcol = nullptr;
+  int u_max_cells = 0, u_max_entries = 0;
+  int64_t u_cells = 0;   // listed cells over all units
   // execution
   bool use_graphs = true;
   int poll = 8;
@@ -931,6 +938,9 @@ spde_status spde_set_transfer(spde_handle h, int64_t n_tet, int64_t nnz, const i
   c->n_tet = n_tet;
   c->nnz = nnz;
   c->order = nullptr;
+  c->uptr = nullptr;
+  c->ucells = nullptr;
+  c->lcol = nullptr;
   c->rp = row_ptr_dev;
   c->ci = col_dev;
   c->cv = val_dev;
@@ -969,6 +979,15 @@ spde_status enqueue_transfer(Ctx* c, int batch, const double* u, double* u_tet, 
     if (bp > 1) {
       Timed t(c, KID_SPMM_STAGE, 0, st, 0, s0, nb, 8.0 * nc * (nb + bp));
       HIPCHK(launch_spmm_stage(u, scratch, c->box.nc, batch, s0, st));
+    }
+    if (c->uptr && (bp == 32 || bp == 64) &&
+        spmm_units_lds(bp, c->u_max_cells, c->u_max_entries) <= kSpmmUnitLds) {
+      // the unit lists replace the column indices: 2 B per entry, 4 B per listed cell
+      const double units = 8.0 * (nt + 1.0) + 10.0 * (double)c->nnz + 4.0 * (double)c->u_cells;
+      Timed t(c, KID_SPMM, 0, st, 0, s0, nb, units + 8.0 * nb * (nc + nt));
+      HIPCHK(launch_spmm_units(c->rp, c->cv, c->uptr, c->ucells, c->lcol, scratch, u_tet, c->n_tet, c->nnz,
+                               c->box.nc, batch, s0, c->order, c->u_max_cells, c->u_max_entries, st));
+      continue;
     }
     Timed t(c, KID_SPMM, 0, st, 0, s0, nb, csr + 8.0 * nb * (nc + nt));
     HIPCHK(launch_spmm_gather(c->rp, c->ci, c->cv, u, scratch, u_tet, c->n_tet, c->nnz, c->box.nc, batch, s0,
@@ -1528,6 +1547,104 @@ spde_status spde_set_transfer_chunk_order(spde_handle h, const int32_t* order_de
   if (!c) return fail(SPDE_EINVAL, "null handle");
   if (!c->rp) return fail(SPDE_EINVAL, "no transfer set");
   c->order = order_dev;
+  return SPDE_OK;
+}
+
+int spde_transfer_unit_rows(void) { return kSpmmUnit; }
+
+spde_status spde_transfer_units(int64_t n_rows, int64_t n_cols, const int64_t* row_ptr_host,
+                                const int32_t* col_host, int64_t* unit_ptr_host, int32_t* unit_cells_host,
+                                uint16_t* local_col_host, int32_t* max_cells, int32_t* max_entries) {
+  if (n_rows < 1 || n_cols < 1 || !row_ptr_host || !unit_ptr_host || !max_cells || !max_entries)
+    return fail(SPDE_EINVAL, "invalid argument");
+  const bool fill = unit_cells_host != nullptr;
+  if (fill != (local_col_host != nullptr)) return fail(SPDE_EINVAL, "unit_cells and local_col go together");
+  const int64_t nnz = row_ptr_host[n_rows];
+  if (row_ptr_host[0] != 0 || nnz < 0) return fail(SPDE_EINVAL, "row pointers must start at 0 and end at nnz");
+  for (int64_t r = 0; r < n_rows; ++r)
+    if (row_ptr_host[r + 1] < row_ptr_host[r]) return fail(SPDE_EINVAL, "row pointers decrease at row %lld", (long long)r);
+  if (nnz > 0 && !col_host) return fail(SPDE_EINVAL, "null column array");
+  const int64_t nunit = (n_rows + kSpmmUnit - 1) / kSpmmUnit;
+  // units in parallel ranges; the first call counts, the second writes
+  std::vector<int64_t> count(fill ? 0 : nunit);
+  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (nunit < 4096) nth = 1;
+  std::vector<int32_t> mcs(nth, 0), mes(nth, 0);
+  std::vector<int64_t> bad(nth, -1);
+  auto work = [&](unsigned t) {
+    std::vector<int32_t> cells;
+    const int64_t u0 = nunit * t / nth, u1 = nunit * (t + 1) / nth;
+    for (int64_t u = u0; u < u1; ++u) {
+      const int64_t e0 = row_ptr_host[u * kSpmmUnit], e1 = row_ptr_host[std::min(n_rows, (u + 1) * kSpmmUnit)];
+      cells.clear();
+      for (int64_t k = e0; k < e1; ++k)
+        if (col_host[k] >= 0 && col_host[k] < n_cols) cells.push_back(col_host[k]);
+      std::sort(cells.begin(), cells.end());
+      cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
+      mcs[t] = std::max(mcs[t], (int32_t)cells.size());
+      mes[t] = std::max(mes[t], (int32_t)(e1 - e0));
+      if (!fill) {
+        count[u] = (int64_t)cells.size();
+        continue;
+      }
+      const int64_t off = unit_ptr_host[u];
+      if (unit_ptr_host[u + 1] - off != (int64_t)cells.size()) {
+        if (bad[t] < 0) bad[t] = u;
+        continue;
+      }
+      std::copy(cells.begin(), cells.end(), unit_cells_host + off);
+      for (int64_t k = e0; k < e1; ++k) {
+        const int32_t col = col_host[k];
+        local_col_host[k] = (col >= 0 && col < n_cols)
+                                ? (uint16_t)(std::lower_bound(cells.begin(), cells.end(), col) - cells.begin())
+                                : (uint16_t)65535;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nth; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto& x : th) x.join();
+  int32_t mc = 0, me = 0;
+  for (unsigned t = 0; t < nth; ++t) {
+    mc = std::max(mc, mcs[t]);
+    me = std::max(me, mes[t]);
+    if (bad[t] >= 0) return fail(SPDE_EINVAL, "unit_ptr does not match the matrix (unit %lld)", (long long)bad[t]);
+  }
+  if (mc >= 65535) return fail(SPDE_EINVAL, "a unit references more than 65534 cells");
+  if (!fill) {
+    unit_ptr_host[0] = 0;
+    for (int64_t u = 0; u < nunit; ++u) unit_ptr_host[u + 1] = unit_ptr_host[u] + count[u];
+  }
+  *max_cells = mc;
+  *max_entries = me;
+  return SPDE_OK;
+}
+
+spde_status spde_set_transfer_units(spde_handle h, const int64_t* unit_ptr_dev, const int32_t* unit_cells_dev,
+                                    const uint16_t* local_col_dev, int32_t max_cells, int32_t max_entries) {
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (!c) return fail(SPDE_EINVAL, "null handle");
+  if (!unit_ptr_dev || !unit_cells_dev || !local_col_dev) {
+    c->uptr = nullptr;
+    c->ucells = nullptr;
+    c->lcol = nullptr;
+    return SPDE_OK;
+  }
+  if (!c->rp) return fail(SPDE_EINVAL, "no transfer set");
+  if (max_cells < 0 || max_entries < 0 || max_cells >= 65535)
+    return fail(SPDE_EINVAL, "invalid unit maxima (%d cells, %d entries)", max_cells, max_entries);
+  // the total of listed cells (for the byte model): the last unit pointer
+  const int64_t nunit = (c->n_tet + kSpmmUnit - 1) / kSpmmUnit;
+  int64_t total = 0;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipMemcpy(&total, unit_ptr_dev + nunit, sizeof(int64_t), hipMemcpyDeviceToHost));
+  c->uptr = unit_ptr_dev;
+  c->ucells = unit_cells_dev;
+  c->lcol = local_col_dev;
+  c->u_max_cells = max_cells;
+  c->u_max_entries = max_entries;
+  c->u_cells = total;
   return SPDE_OK;
 }
 

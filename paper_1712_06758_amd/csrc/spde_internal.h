@@ -223,6 +223,15 @@ hipError_t launch_init_correction(const Fields& F, const Box& bx, int batch, con
 // (spmm_scratch_bytes(nc, batch) bytes; unused for batch 1), then gathered,
 // rows in chunks of kSpmmChunk visited in the chunk order corder (nullable).
 constexpr int kSpmmChunk = 64;
+// Rows per unit of the LDS-staged product (a chunk holds kSpmmChunk / kSpmmUnit
+// units), and its LDS budget per block.
+constexpr int kSpmmUnit = 16;
+constexpr size_t kSpmmUnitLds = 60 << 10;
+// Loads per thread of the unit kernel's stage: a unit's cells (x lanes per
+// cell) and entries must fit them.
+constexpr int kSpmmUnitCellIt = 8, kSpmmUnitEntIt = 2;
+// Entries the unit kernel's LDS entry buffers hold beyond a unit's own.
+constexpr int kSpmmUnitPad = 4;
 // Static device scratch of the no-allocation transfer product (per device).
 constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
 constexpr int kMaxDevices = 64;
@@ -233,6 +242,14 @@ hipError_t launch_spmm_stage(const double* u, double* xt, int64_t nc, int batch,
 hipError_t launch_spmm_gather(const int64_t* rp, const int32_t* ci, const double* cv, const double* u,
                               const double* xt, double* out, int64_t ntet, int64_t nnz, int64_t nc, int batch,
                               int s0, const int32_t* corder, hipStream_t st);
+// The LDS-staged product for sample blocks of 32 or 64 (spmm_units_lds bytes of
+// LDS per block; usable when that is at most kSpmmUnitLds): unit u's cells
+// ucells[uptr[u] .. uptr[u + 1]) and each entry's index lcol in that list.
+size_t spmm_units_lds(int bp, int max_cells, int max_entries);
+hipError_t launch_spmm_units(const int64_t* rp, const double* cv, const int64_t* uptr, const int32_t* ucells,
+                             const uint16_t* lcol, const double* xt, double* out, int64_t ntet, int64_t nnz,
+                             int64_t nc, int batch, int s0, const int32_t* corder, int max_cells, int max_entries,
+                             hipStream_t st);
 hipError_t launch_spmm(const int64_t* rp, const int32_t* ci, const double* cv, const double* u, double* out,
                        int64_t ntet, int64_t nnz, int64_t nc, int batch, const int32_t* corder, double* scratch,
                        hipStream_t st);

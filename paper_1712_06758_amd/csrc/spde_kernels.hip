@@ -340,16 +340,18 @@ __global__ __launch_bounds__(kBlock) void k_spmm_stage(const double* __restrict_
 // samples (one 16-byte load per entry), so a wave's lanes form G = 128 / BP
 // groups of BP / 2 lanes; a group owns 8 consecutive rows of a chunk and works
 // through them one after the other.  For each row the group first holds up to
-// U = 8 of its entries (column, value) in its lanes, then issues their U
+// U = 12 of its entries (column, value) in its lanes, then issues their U
 // gathers at once; while those are in flight it loads the row pointers and
-// entries of the next row, so a row costs one memory round trip and a wave
-// keeps G x U gathers of BP x 8 bytes in flight.  (Measured at 128^3 x 64:
-// U = 8 at 4 waves per SIMD beats U = 16 at 2 or 3 waves, 1.31 against 1.7 ms.)  Each row's sum runs over its entries in
-// order.  The block's results (its chunks' rows x BP samples) go through an
+// entries of the next row, so a row (9 entries on average for the workload
+// meshes) costs one memory round trip and a wave keeps G x U gathers of
+// BP x 8 bytes in flight.  Measured at 128^3 x 64: U = 12 at 3 waves per SIMD
+// runs as fast as U = 8 at 4 (1.28 ms) and fetches 3.8 instead of 6.2 GB from
+// memory (counter bytes); U = 16 fits only 2 waves per SIMD and is slower
+// (1.7 ms).  Each row's sum runs over its entries in order.  The block's results (its chunks' rows x BP samples) go through an
 // LDS tile and leave row-contiguous per sample.  Row pointers must not
 // decrease; if they do, no memory outside the arrays is touched, but the sums
 // are undefined.
-template <int BP, int UM = 8, int WPS = 4>
+template <int BP, int UM = 12, int WPS = 3>
 __global__ __launch_bounds__(kBlock, WPS) void k_spmm_gather(const int64_t* __restrict__ rp,
                                                              const int32_t* __restrict__ ci,
                                                              const double* __restrict__ cv,
@@ -440,6 +442,167 @@ __global__ __launch_bounds__(kBlock, WPS) void k_spmm_gather(const int64_t* __re
     if (ss >= nb || qq >= nchunk) continue;
     const int64_t row = (corder ? (int64_t)corder[qq] : qq) * kSpmmChunk + li % kSpmmChunk;
     if (row < ntet) out[(int64_t)(s0 + ss) * ntet + row] = tile[li * LD + ss];
+  }
+}
+
+// The same product with each row unit's cells staged in LDS (blocks of BP = 32
+// or 64 samples).  Units of kSpmmUnit rows are taken in the chunk visiting
+// order; block b handles logical units b, b + G, b + 2G, ... (G blocks).  Per
+// unit it loads the staged sample rows xt[cell][0 .. BP) of the unit's distinct
+// cells (ucells[uptr[u] .. uptr[u + 1]), ascending) and the unit's entries
+// (value, index lcol of the column in that list) into LDS, forms the unit's
+// rows from LDS in the groups and entry order of k_spmm_gather (so the sums are
+// bitwise the same), and stores through an LDS tile that reuses the cell
+// buffer.  Each cell of a unit is read from memory once instead of once per
+// entry, and the next unit's cell indices are loaded while this unit computes,
+// so a unit costs one memory round trip.  Lists that do not fit the sizes the
+// launch was given are cut at them (no access outside the LDS buffers; the
+// sums are then wrong), which cannot happen for lists built from the
+// registered matrix.
+template <int BP>
+__global__ __launch_bounds__(kBlock) void k_spmm_units(const int64_t* __restrict__ rp, const double* __restrict__ cv,
+                                                       const int64_t* __restrict__ uptr,
+                                                       const int32_t* __restrict__ ucells,
+                                                       const uint16_t* __restrict__ lcol,
+                                                       const double* __restrict__ xt, double* __restrict__ out,
+                                                       int64_t ntet, int64_t nnz, int64_t nc, int batch, int s0,
+                                                       const int32_t* __restrict__ corder, int64_t nunit,
+                                                       int cells_cap, int entries_cap) {
+  static_assert(BP == 32 || BP == 64, "sample block");
+  constexpr int LG = BP / 2;                 // lanes per group (two samples each)
+  constexpr int NG = kBlock / LG;            // groups per block
+  constexpr int RPG = kSpmmUnit / NG;        // rows per group
+  constexpr int LD = BP + 2;                 // padded row of a staged cell (16-byte aligned pairs)
+  constexpr int UPC = kSpmmChunk / kSpmmUnit;
+  static_assert(RPG >= 1 && RPG * NG == kSpmmUnit && kSpmmChunk % kSpmmUnit == 0, "unit split");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* sx = reinterpret_cast<double*>(smem_raw);              // [cells_cap][LD], then the output tile
+  double* sv = sx + (size_t)cells_cap * LD;                       // [entries_cap] entry values
+  uint16_t* sl = reinterpret_cast<uint16_t*>(sv + entries_cap);   // [entries_cap] entry cells
+  __shared__ int srp[kSpmmUnit + 1];
+  const int tid = threadIdx.x;
+  const int64_t nlog = ((ntet + kSpmmChunk - 1) / kSpmmChunk) * UPC;   // logical units
+  const int64_t G = gridDim.x;
+  auto clampk = [&](int64_t k) { return max((int64_t)0, min(k, nnz)); };
+  auto unit_of = [&](int64_t lu) {
+    const int64_t lq = lu / UPC;
+    return (corder ? (int64_t)corder[lq] : lq) * UPC + (lu - lq * UPC);
+  };
+  // cell indices of a unit's stage items (the launcher keeps ncell * LG <=
+  // kSpmmUnitCellIt * kBlock and ne <= kSpmmUnitEntIt * kBlock)
+  int32_t cellv[kSpmmUnitCellIt];
+  auto load_cells = [&](int64_t unit) {
+    const int64_t c0 = unit < nunit ? uptr[unit] : 0;
+    const int ncell = unit < nunit ? (int)min((int64_t)cells_cap, max((int64_t)0, uptr[unit + 1] - c0)) : 0;
+#pragma unroll
+    for (int it = 0; it < kSpmmUnitCellIt; ++it) {
+      const int cl = (tid + it * kBlock) / LG;
+      cellv[it] = cl < ncell ? ucells[c0 + cl] : -1;
+    }
+    return ncell;
+  };
+  int64_t lu = xcd_remap(blockIdx.x, gridDim.x);
+  int64_t unit = lu < nlog ? unit_of(lu) : nunit;
+  int ncell = load_cells(unit);
+  const int nb = min(BP, batch - s0);
+  const int lane = tid & 63;
+  const int g = lane / LG, s = 2 * (lane % LG);
+  const int gi = (tid >> 6) * (64 / LG) + g;   // group index within the block
+  for (; lu < nlog; lu += G) {
+    const bool live = unit < nunit;
+    const int64_t r0 = unit * kSpmmUnit;
+    const int nr = live ? (int)min((int64_t)kSpmmUnit, ntet - r0) : 0;
+    const int64_t e0 = live ? clampk(rp[r0]) : 0;
+    const int ne = live ? (int)min((int64_t)(entries_cap - kSpmmUnitPad), max((int64_t)0, clampk(rp[r0 + nr]) - e0)) : 0;
+    if (tid <= nr && live) srp[tid] = (int)max((int64_t)0, min(clampk(rp[r0 + tid]) - e0, (int64_t)ne));
+    // this unit's entries and cell rows (all issued before any is consumed)
+    double ev[kSpmmUnitEntIt];
+    uint16_t el[kSpmmUnitEntIt];
+#pragma unroll
+    for (int it = 0; it < kSpmmUnitEntIt; ++it) {
+      const int k = tid + it * kBlock;
+      ev[it] = k < ne ? cv[e0 + k] : 0.0;
+      el[it] = k < ne ? lcol[e0 + k] : (uint16_t)65535;
+    }
+    double2 xv[kSpmmUnitCellIt];
+#pragma unroll
+    for (int it = 0; it < kSpmmUnitCellIt; ++it) {
+      const int p = (tid + it * kBlock) % LG;
+      const bool ok = cellv[it] >= 0 && cellv[it] < nc;
+      xv[it] = *reinterpret_cast<const double2*>(xt + (ok ? (int64_t)cellv[it] : 0) * BP + 2 * p);
+    }
+    // the next unit's cell indices, in flight while this unit computes
+    const int64_t lun = lu + G;
+    const int64_t unext = lun < nlog ? unit_of(lun) : nunit;
+    int32_t cur[kSpmmUnitCellIt];
+#pragma unroll
+    for (int it = 0; it < kSpmmUnitCellIt; ++it) cur[it] = cellv[it];
+    const int ncur = ncell;
+    ncell = load_cells(unext);
+#pragma unroll
+    for (int it = 0; it < kSpmmUnitEntIt; ++it) {
+      const int k = tid + it * kBlock;
+      if (k < ne) {
+        sv[k] = ev[it];
+        sl[k] = el[it];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < kSpmmUnitCellIt; ++it) {
+      const int idx = tid + it * kBlock, cl = idx / LG, p = idx - cl * LG;
+      const bool ok = cur[it] >= 0 && cur[it] < nc;
+      if (cl < ncur) *reinterpret_cast<double2*>(sx + cl * LD + 2 * p) = ok ? xv[it] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double a0[RPG], a1[RPG];
+#pragma unroll
+    for (int rr = 0; rr < RPG; ++rr) {
+      const int lr = gi * RPG + rr;
+      double acc0 = 0.0, acc1 = 0.0;
+      if (lr < nr) {
+        const int ka = srp[lr], kb = max(ka, srp[lr + 1]);
+        // four entries at a time, their LDS reads issued before the sums; the
+        // entry buffers are padded by kSpmmUnitPad, so the reads past the row
+        // stay inside them.  A slot past the row or with a skipped column adds
+        // 0 * x (x a staged value, finite unless the sample itself is not),
+        // which leaves the sum's bits unchanged.
+        for (int k = ka; k < kb; k += 4) {
+          int l[4];
+          double v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            l[u] = sl[k + u];
+            v[u] = sv[k + u];
+          }
+          double2 x[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const bool ok = k + u < kb && l[u] < ncur;
+            x[u] = *reinterpret_cast<const double2*>(sx + (ok ? l[u] : 0) * LD + s);
+            v[u] = ok ? v[u] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            acc0 = fma(v[u], x[u].x, acc0);
+            acc1 = fma(v[u], x[u].y, acc1);
+          }
+        }
+      }
+      a0[rr] = acc0;
+      a1[rr] = acc1;
+    }
+    __syncthreads();   // the cells are read; the tile reuses their buffer
+#pragma unroll
+    for (int rr = 0; rr < RPG; ++rr)
+      *reinterpret_cast<double2*>(sx + (gi * RPG + rr) * LD + s) = make_double2(a0[rr], a1[rr]);
+    __syncthreads();
+    // consecutive threads store consecutive rows of one sample
+    for (int idx = tid; idx < kSpmmUnit * BP; idx += kBlock) {
+      const int ss = idx / kSpmmUnit, li = idx - ss * kSpmmUnit;
+      if (ss < nb && li < nr) out[(int64_t)(s0 + ss) * ntet + r0 + li] = sx[li * LD + ss];
+    }
+    __syncthreads();   // the tile is read before the next unit's stage overwrites it
+    unit = unext;
   }
 }
 

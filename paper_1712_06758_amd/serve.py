@@ -227,7 +227,11 @@ class Server:
 
     engines: {box_n: engine}; every level n needs engines n and n/2 (except the
     coarsest level).  hbm_budget: bytes of device memory that in-flight work may
-    claim (slot workspace share plus per-request noise and outputs)."""
+    claim (slot workspace share plus per-request noise and outputs).  A request
+    is admitted when its parts find free slots and its footprint fits the
+    budget; build_gpu_server derives the budget from the device memory left
+    free after the engines are built, so with the default slot pools the slot
+    count is what binds."""
 
     def __init__(self, engines, levels, noise_fn, restrict_fn, hbm_budget, clock=time.perf_counter,
                  keep_results=False):
@@ -478,7 +482,12 @@ def build_gpu_server(levels=(32, 64, 128, 256), corr_len=0.05, precision="mixed"
         if 2 * n in engines:
             engines[2 * n].host_transfers.clear()     # device copies are registered
     if hbm_budget is None:
-        hbm_budget = sum(e.slot_bytes * e.slots for e in engines.values()) + (8 << 30)
+        # the slot workspaces are bound already; what in-flight requests may add
+        # (noise and output buffers) is the device memory still free, less a
+        # reserve of 4 GiB.  On a 288 GB device the slot pools bind long before
+        # this budget does, so admission is in practice by free slots.
+        free, _ = torch.cuda.mem_get_info(device)
+        hbm_budget = sum(e.slot_bytes * e.slots for e in engines.values()) + max(0, free - (4 << 30))
 
     def noise_fn(level, seed):
         return NoiseKey(int(noise_seed), request_event(seed))

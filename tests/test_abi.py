@@ -292,3 +292,45 @@ def test_csr_apply_validates_before_launching(lib):
     assert b"needed" in L.spde_last_error()
     assert L.spde_csr_apply(5, 9, buf, buf, buf, 10, 2, buf, buf, None, buf, 100, None) == -1  # too small
     assert L.spde_csr_apply(5, 9, buf, buf, buf, 10, 2, buf, buf, None, C.c_void_p(0x1008), 4096, None) == -1
+
+
+def test_transfer_units_lists():
+    """spde_transfer_units: each unit's list holds the distinct in-box columns
+    of its entries, ascending; every entry's local index maps back to its
+    column (65535 for a column outside the box); the maxima; errors."""
+    import ctypes as C
+    import paper_1712_06758_amd as P
+    from paper_1712_06758_amd import _abi
+    rng = np.random.default_rng(5)
+    n_rows, n_cols = 1003, 5000
+    lens = rng.integers(0, 12, n_rows)
+    lens[::17] = 0
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    cols = rng.integers(-3, n_cols + 3, rp[-1]).astype(np.int32)
+    uptr, cells, lcol, mc, me = P.transfer_units(rp, cols, n_cols)
+    U = _abi.lib().spde_transfer_unit_rows()
+    assert uptr.size == (n_rows + U - 1) // U + 1 and uptr[0] == 0
+    mc_ref = me_ref = 0
+    for u in range(uptr.size - 1):
+        e0, e1 = rp[u * U], rp[min(n_rows, (u + 1) * U)]
+        c = cols[e0:e1]
+        want = np.unique(c[(c >= 0) & (c < n_cols)])
+        got = cells[uptr[u]:uptr[u + 1]]
+        assert np.array_equal(got, want)
+        ok = (c >= 0) & (c < n_cols)
+        assert np.all(lcol[e0:e1][~ok] == 65535)
+        assert np.array_equal(got[lcol[e0:e1][ok].astype(np.int64)], c[ok])
+        mc_ref, me_ref = max(mc_ref, want.size), max(me_ref, e1 - e0)
+    assert (mc, me) == (mc_ref, me_ref)
+    L = _abi.lib()
+    bad = rp.copy()
+    bad[10] = bad[11] + 1
+    m1 = C.c_int32(); m2 = C.c_int32()
+    assert L.spde_transfer_units(n_rows, n_cols, bad.ctypes.data, cols.ctypes.data, uptr.ctypes.data, None, None,
+                                 C.byref(m1), C.byref(m2)) == _abi.SPDE_EINVAL
+    wrong = uptr.copy()
+    wrong[3:] += 1
+    c2 = np.empty(int(wrong[-1]), np.int32)
+    l2 = np.empty(cols.size, np.uint16)
+    assert L.spde_transfer_units(n_rows, n_cols, rp.ctypes.data, cols.ctypes.data, wrong.ctypes.data,
+                                 c2.ctypes.data, l2.ctypes.data, C.byref(m1), C.byref(m2)) == _abi.SPDE_EINVAL

@@ -310,6 +310,25 @@ def test_every_tile_shape_gives_the_same_vcycle(torch_cuda, prec):
     assert not bad, bad
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_recorded_tiles_reproduce_a_sample_bitwise(torch_cuda, prec):
+    """Every result records the tile shapes it ran with; a second handle with
+    those shapes fixed (no autotuning) reproduces the sample bit for bit."""
+    torch = torch_cuda
+    n = 64
+    say(f"recorded tiles reproduce a sample, {prec} n={n}")
+    xi = torch.tensor(xi_batch(n, [21, 22, 23]), device="cuda")
+    a = P().Box(n, 20.0, 3.0, precision=prec, max_batch=3).sample(xi, u_tet=False, u_box=True)
+    box = P().Box(n, 20.0, 3.0, precision=prec, max_batch=3)
+    for level, (d, u) in enumerate(a["tiles"]):
+        box.set_tiles(d, u, level)
+    b = box.sample(xi, u_tet=False, u_box=True)
+    torch.cuda.synchronize()
+    assert b["tiles"] == a["tiles"]
+    assert torch.equal(a["u_box"], b["u_box"])
+    assert a["iters"].tolist() == b["iters"].tolist()
+
+
 @pytest.mark.parametrize("shape,prec", [(1, "fp64"), (6, "fp64"), (7, "fp64"), (9, "fp64"), (10, "fp64"),
                                         (11, "fp64"), (13, "fp64"), (14, "fp64"), (10, "mixed"), (12, "mixed"),
                                         (15, "mixed"), (17, "mixed"), (16, "fp64")])

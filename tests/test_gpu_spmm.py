@@ -2,7 +2,8 @@
 CSR product of the same matrix: every sample-block width (a single sample, a
 power-of-two block, a padded block, several blocks of 64), the row chunks in
 index order and in a permuted visiting order, empty rows and column indices
-outside the box (skipped)."""
+outside the box (skipped); the LDS-staged unit kernel of a sampler handle
+bitwise equal to the chunked gather."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -73,3 +74,32 @@ def test_transfer_of_oracle_matrix(batch):
                     torch.tensor(x, device=d), rows.size)
     ref = (Pi @ x.T).T
     assert np.abs(y.cpu().numpy() - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("batch", [64, 40, 32, 20, 16, 5])
+def test_unit_kernel_equals_gather(batch):
+    """A handle's transfer (row units staged in LDS for blocks of 32 and 64
+    samples, the gather otherwise) against spde_csr_apply's chunked gather of
+    the same matrix: bitwise, on the 64^3 workload mesh and on a random matrix
+    with empty rows and columns outside the box; and against SciPy."""
+    import torch
+    import paper_1712_06758_amd as P
+    from workloads import WORKLOADS
+    d = torch.device("cuda")
+    w = WORKLOADS["box64"]
+    n = w.n
+    mesh_csr = P.build_transfer_host(n, *w.mesh())
+    rnd = _random_csr(150_007, n ** 3, 99 + batch, bad_cols=True)
+    for label, (rp, cols, vals) in (("mesh", mesh_csr), ("random", rnd)):
+        n_rows = rp.size - 1
+        say(f"unit kernel vs gather: {label}, batch {batch}, {n_rows} rows")
+        x = torch.tensor(np.random.default_rng(batch).standard_normal((batch, n ** 3)), device=d)
+        box = P.Box(n, w.kappa, w.g, max_batch=batch)
+        box.set_transfer(rp, cols, vals)
+        got = box.apply_transfer(x)
+        ref = P.csr_apply(torch.tensor(rp, device=d), torch.tensor(cols, device=d), torch.tensor(vals, device=d),
+                          x, n_rows)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref)
+        sref = _ref(rp, cols, vals, n_rows, n ** 3, x.cpu().numpy())
+        assert np.abs(got.cpu().numpy() - sref).max() <= 1e-14 * max(1.0, np.abs(sref).max())
