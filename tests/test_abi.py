@@ -334,3 +334,17 @@ def test_transfer_units_lists():
     l2 = np.empty(cols.size, np.uint16)
     assert L.spde_transfer_units(n_rows, n_cols, rp.ctypes.data, cols.ctypes.data, wrong.ctypes.data,
                                  c2.ctypes.data, l2.ctypes.data, C.byref(m1), C.byref(m2)) == _abi.SPDE_EINVAL
+
+
+def test_set_transfer_units_validation(lib):
+    """spde_set_transfer_units: a null handle and a handle without a transfer
+    are refused; null lists clear the registration."""
+    from paper_1712_06758_amd import _abi
+    L = _abi.lib()
+    fake = C.c_void_p(0x1000)
+    assert L.spde_set_transfer_units(None, fake, fake, fake, 4, 4) == -1
+    st, h = setup(lib, 16)
+    assert st == 0
+    assert L.spde_set_transfer_units(h, fake, fake, fake, 4, 4) == -1      # no transfer registered
+    assert L.spde_set_transfer_units(h, None, None, None, 0, 0) == 0       # clearing is always allowed
+    lib.spde_destroy(h)
