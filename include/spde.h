@@ -190,7 +190,7 @@ spde_status spde_set_transfer_chunk_order(spde_handle h, const int32_t* order_de
  * Two calls: the first (both list pointers NULL) writes unit_ptr_host and the
  * maxima, the second fills the lists.  Host arrays, caller-owned; no device
  * call.  SPDE_EINVAL for null pointers, n_rows < 1, n_cols < 1 or row pointers
- * that decrease or leave [0, nnz]. */
+ * that decrease or leave [0, nnz]; SPDE_ENOMEM if host memory runs out. */
 int spde_transfer_unit_rows(void);
 spde_status spde_transfer_units(int64_t n_rows, int64_t n_cols, const int64_t* row_ptr_host,
                                 const int32_t* col_host, int64_t* unit_ptr_host, int32_t* unit_cells_host,

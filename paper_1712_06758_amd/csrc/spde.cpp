@@ -1571,7 +1571,9 @@ spde_status spde_transfer_units(int64_t n_rows, int64_t n_cols, const int64_t* r
   if (nunit < 4096) nth = 1;
   std::vector<int32_t> mcs(nth, 0), mes(nth, 0);
   std::vector<int64_t> bad(nth, -1);
+  std::vector<char> oom(nth, 0);
   auto work = [&](unsigned t) {
+    try {
     std::vector<int32_t> cells;
     const int64_t u0 = nunit * t / nth, u1 = nunit * (t + 1) / nth;
     for (int64_t u = u0; u < u1; ++u) {
@@ -1600,13 +1602,22 @@ spde_status spde_transfer_units(int64_t n_rows, int64_t n_cols, const int64_t* r
                                 : (uint16_t)65535;
       }
     }
+    } catch (...) {
+      oom[t] = 1;
+    }
   };
   std::vector<std::thread> th;
-  for (unsigned t = 1; t < nth; ++t) th.emplace_back(work, t);
+  try {
+    for (unsigned t = 1; t < nth; ++t) th.emplace_back(work, t);
+  } catch (...) {
+    // no more threads: the ranges not started run on this one
+    for (unsigned t = (unsigned)th.size() + 1; t < nth; ++t) work(t);
+  }
   work(0);
   for (auto& x : th) x.join();
   int32_t mc = 0, me = 0;
   for (unsigned t = 0; t < nth; ++t) {
+    if (oom[t]) return fail(SPDE_ENOMEM, "out of host memory building the transfer units");
     mc = std::max(mc, mcs[t]);
     me = std::max(me, mes[t]);
     if (bad[t] >= 0) return fail(SPDE_EINVAL, "unit_ptr does not match the matrix (unit %lld)", (long long)bad[t]);
