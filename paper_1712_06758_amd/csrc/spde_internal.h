@@ -92,6 +92,21 @@ template <typename T>
 __device__ __forceinline__ T ld_off(const T* base, uint32_t byte_off) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
 }
+// Streaming accesses for vectors that a pass reads once and writes once.  With
+// NT they carry the nontemporal hint: at sizes far beyond the caches the lines
+// they bring in then need not displace the ones that other streams of the pass
+// still reuse.  Without it they are plain accesses, which keeps a working set
+// that fits the last-level cache there between passes.  Values are the same.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_stream(T v, T* p) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
 #endif
 
 // kappa^2 h^3 of cell c (same rounding as the host's kappa * kappa * h^3).

@@ -118,7 +118,9 @@ __global__ __launch_bounds__(kBlock) void k_operator(Fields F, Box bx, int nb) {
 // faces of its 4 rows (with a 3-face halo along x) and the y faces of rows
 // -3 .. +6 in LDS, from which the x and y windows are read.  Same arithmetic,
 // in the same order, as k_operator.
-template <typename TZ, int POLY, bool VAR, int ZC>
+// NT: the Lanczos, direction and solution vectors are streamed with the
+// nontemporal hint (chosen by the launcher from the launch's working set).
+template <typename TZ, int POLY, bool VAR, int ZC, bool NT>
 __global__ __launch_bounds__(kBlock) void k_operator_col(Fields F, Box bx, int nb) {
   constexpr int XW = 64 + 6, AXF = XW * 4, RXF = (AXF + kBlock - 1) / kBlock;   // x faces, halo 3 in x
   constexpr int AYF = 64 * (4 + 6), RYF = (AYF + kBlock - 1) / kBlock;           // y faces, halo 3 in y
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_operator_col(Fields F, Box bx, int n
   auto x_update = [&](int64_t c, double wj, double wjm1) {
     if (upd_x) {
       const double inc = sxp * wjm1 + sxw * wj;
-      F.x[co + c] = (j == 2 && !acc) ? inc : F.x[co + c] + inc;
+      st_stream<NT>((j == 2 && !acc) ? inc : ld_stream<NT>(&F.x[co + c]) + inc, &F.x[co + c]);
     }
   };
   if (!active) {
@@ -222,9 +224,9 @@ __global__ __launch_bounds__(kBlock) void k_operator_col(Fields F, Box bx, int n
     const double zc = (double)z[c];
     const double zlo[3] = {(double)z[i > 0 ? c - 1 : c], (double)z[jj > 0 ? c - n : c], k > 0 ? zprev : zc};
 #pragma unroll
-    for (int d = 0; d < 3; ++d) vo[d] = F.vs[pq][face_off(slot, d, nc) + c];
-    const double vuc = F.vu[p][co + c], vuo = F.vu[pq][co + c];
-    const double wj = F.w[pq][co + c], wjm1 = F.w[p][co + c];
+    for (int d = 0; d < 3; ++d) vo[d] = ld_stream<NT>(&F.vs[pq][face_off(slot, d, nc) + c]);
+    const double vuc = ld_stream<NT>(&F.vu[p][co + c]), vuo = ld_stream<NT>(&F.vu[pq][co + c]);
+    const double wj = ld_stream<NT>(&F.w[pq][co + c]), wjm1 = ld_stream<NT>(&F.w[p][co + c]);
     const double kc = VAR ? bx.kap[c] : 0.0;
     __syncthreads();
     double w[2][7];
@@ -246,15 +248,15 @@ __global__ __launch_bounds__(kBlock) void k_operator_col(Fields F, Box bx, int n
       nf[d] = idx[d] > 0 ? (has_prev ? nv - bv * vo[d] : nv) : 0.0;
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) F.vs[pq][face_off(slot, d, nc) + c] = nf[d];
+    for (int d = 0; d < 3; ++d) st_stream<NT>(nf[d], &F.vs[pq][face_off(slot, d, nc) + c]);
     const double k2 = VAR ? (kc * kc) * bx.h3 : bx.k2h3;
     const double Au = zs * (bx.h2q * dv - k2 * zc);
     const double nu = Au - av * vuc;
-    F.vu[pq][co + c] = has_prev ? nu - bv * vuo : nu;
+    st_stream<NT>(has_prev ? nu - bv * vuo : nu, &F.vu[pq][co + c]);
     double wn = zs * zc;
     if (wm >= 1) wn += sww * wj;
     if (wm >= 2) wn += swwp * wjm1;
-    F.w[p][co + c] = wm >= 0 ? wn : wjm1;
+    st_stream<NT>(wm >= 0 ? wn : wjm1, &F.w[p][co + c]);
     if (wm >= 1) x_update(c, wj, wm >= 2 ? wjm1 : 0.0);
 #pragma unroll
     for (int q = 0; q < 6; ++q) wz[q] = wz[q + 1];
@@ -265,24 +267,36 @@ __global__ __launch_bounds__(kBlock) void k_operator_col(Fields F, Box bx, int n
 
 // planes per block of the column form of the operator pass
 constexpr int kOpZC = 16;
+// The column pass streams its vectors with the nontemporal hint when the
+// launch's vectors (about 128 bytes per cell and sample) exceed this size.
+// MI355X has a 256 MB last-level cache: one 128^3 sample (about 265 MB) still
+// runs faster without the hint (its vectors largely stay cached between
+// passes), two or more run faster with it.
+constexpr double kOpStreamBytes = 384.0 * 1024 * 1024;
 
 hipError_t launch_operator(bool z_fp64, const Fields& F, const Box& bx, int batch, hipStream_t st) {
   if (bx.n % 64 == 0 && bx.n % kOpZC == 0) {
     // 64 x 4 columns of kOpZC planes per block
     const int nbc = (bx.n / 64) * (bx.n / 4) * (bx.n / kOpZC);
     const dim3 gridc(nbc * batch), blkc(kBlock);
-#define SPDE_OPC(TZ)                                                                                      \
-  do {                                                                                                    \
-    if (bx.kap) {                                                                                         \
-      if (bx.poly) hipLaunchKernelGGL((k_operator_col<TZ, 1, true, kOpZC>), gridc, blkc, 0, st, F, bx, nbc);  \
-      else hipLaunchKernelGGL((k_operator_col<TZ, 0, true, kOpZC>), gridc, blkc, 0, st, F, bx, nbc);          \
-    } else {                                                                                              \
-      if (bx.poly) hipLaunchKernelGGL((k_operator_col<TZ, 1, false, kOpZC>), gridc, blkc, 0, st, F, bx, nbc); \
-      else hipLaunchKernelGGL((k_operator_col<TZ, 0, false, kOpZC>), gridc, blkc, 0, st, F, bx, nbc);         \
-    }                                                                                                     \
+    const bool nt = 128.0 * (double)bx.nc * (double)batch > kOpStreamBytes;
+#define SPDE_OPC(TZ, NT)                                                                                        \
+  do {                                                                                                          \
+    if (bx.kap) {                                                                                               \
+      if (bx.poly) hipLaunchKernelGGL((k_operator_col<TZ, 1, true, kOpZC, NT>), gridc, blkc, 0, st, F, bx, nbc);  \
+      else hipLaunchKernelGGL((k_operator_col<TZ, 0, true, kOpZC, NT>), gridc, blkc, 0, st, F, bx, nbc);          \
+    } else {                                                                                                    \
+      if (bx.poly) hipLaunchKernelGGL((k_operator_col<TZ, 1, false, kOpZC, NT>), gridc, blkc, 0, st, F, bx, nbc); \
+      else hipLaunchKernelGGL((k_operator_col<TZ, 0, false, kOpZC, NT>), gridc, blkc, 0, st, F, bx, nbc);         \
+    }                                                                                                           \
   } while (0)
-    if (z_fp64) SPDE_OPC(double);
-    else SPDE_OPC(float);
+    if (z_fp64) {
+      if (nt) SPDE_OPC(double, true);
+      else SPDE_OPC(double, false);
+    } else {
+      if (nt) SPDE_OPC(float, true);
+      else SPDE_OPC(float, false);
+    }
 #undef SPDE_OPC
     return hipGetLastError();
   }
