@@ -329,6 +329,28 @@ def test_recorded_tiles_reproduce_a_sample_bitwise(torch_cuda, prec):
     assert a["iters"].tolist() == b["iters"].tolist()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_streaming_operator_pass_gives_the_same_samples(torch_cuda, prec):
+    """A launch whose vectors exceed the last-level cache streams them through
+    the operator pass with the nontemporal hint (at 64^3 from 13 samples on).
+    With the tile shapes fixed, its samples equal the same samples solved one
+    at a time (plain accesses) bit for bit."""
+    torch = torch_cuda
+    n, B = 64, 16
+    say(f"streaming operator pass vs plain accesses, {prec} n={n} batch {B}")
+    xi = torch.tensor(xi_batch(n, list(range(40, 40 + B))), device="cuda")
+    big = P().Box(n, 20.0, 3.0, precision=prec, max_batch=B)
+    big.set_tiles(10, 10)
+    a = big.sample(xi, u_tet=False, u_box=True)
+    one = P().Box(n, 20.0, 3.0, precision=prec, max_batch=1)
+    one.set_tiles(10, 10)
+    for s in (0, 7, 15):
+        b = one.sample(xi[s:s + 1].contiguous(), u_tet=False, u_box=True)
+        torch.cuda.synchronize()
+        assert int(a["iters"][s]) == int(b["iters"][0])
+        assert torch.equal(a["u_box"][s], b["u_box"][0])
+
+
 @pytest.mark.parametrize("shape,prec", [(1, "fp64"), (6, "fp64"), (7, "fp64"), (9, "fp64"), (10, "fp64"),
                                         (11, "fp64"), (13, "fp64"), (14, "fp64"), (10, "mixed"), (12, "mixed"),
                                         (15, "mixed"), (17, "mixed"), (16, "fp64")])
