@@ -464,9 +464,8 @@ spde_status spde_set_face_preconditioner(spde_handle h, int kind);
  * residual r = F - A U is formed with the flux recovered from U (so only its
  * cell row is nonzero); while ||r|| / ||F|| > target for a sample, and at most
  * max_passes times, A d = r is solved by the same preconditioned MINRES and
- * U += d for the samples above the target.  A pass stops at the relative
- * tolerance 0.1 target / (largest residual above the target), kept within
- * [rtol, 0.5].  This lets the mixed
+ * U += d for the samples above the target.  A sample's pass stops at the
+ * relative tolerance 0.5 target / (its residual), kept within [rtol, 0.5].  This lets the mixed
  * precision (float32 multigrid) reach residuals far below its rtol.
  * target = 0 (default) turns refinement off; target in [0, 1), max_passes in
  * [0, 16].  Applies to spde_sample, spde_sample_seeded and spde_sample_warm

@@ -1143,14 +1143,16 @@ spde_status sample_impl(Ctx* c, int batch, const NoiseSrc& src, double* u_tet_de
       }
       if (!need_any || pass >= c->refine_max) break;
       // A sample's pass has to reduce its residual by target / residual only (a
-      // factor of 10 to spare), never tighter than the configured rtol, which
+      // factor of 2 to spare: the true residual of a pass ends a few times
+      // below its MINRES estimate, and a sample left above the target takes
+      // another pass of its own), never tighter than the configured rtol, which
       // the preconditioned MINRES is known to reach.  Each sample takes its own
       // tolerance, so that its result does not depend on the batch.
       std::vector<double> tols(batch);
       for (int b = 0; b < batch; ++b) {
         const double r = c->host_res[b];
         tols[b] = refine[b] && std::isfinite(r) && r > 0.0
-                      ? std::min(0.5, std::max(c->rtol, 0.1 * c->refine_target / r))
+                      ? std::min(0.5, std::max(c->rtol, 0.5 * c->refine_target / r))
                       : c->rtol;
       }
       std::copy(tols.begin(), tols.end(), c->host_res);
