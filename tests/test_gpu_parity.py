@@ -113,6 +113,24 @@ def _run_sample(torch, n, kappa, prec, xi, mesh=None, **kw):
 
 
 @pytest.mark.parametrize("prec,bar", [("fp64", 1e-10), ("mixed", 1e-7)])
+@pytest.mark.parametrize("n", [4, 8])
+def test_small_boxes_every_sample(torch_cuda, prec, bar, n):
+    """The smallest boxes: the persistent coarse kernel starts at 2^3 (n = 4)
+    or 4^3 (n = 8); every sample of the batch meets the bar against the oracle."""
+    torch = torch_cuda
+    kappa = 10.0
+    g = gval(kappa)
+    xi = xi_batch(n, [3, 4, 5])
+    ref = oracle_u(n, kappa, g, xi)
+    say(f"small box {prec} n={n}")
+    out = P().Box(n, kappa, precision=prec, max_batch=3).sample(torch.tensor(xi, device="cuda"), u_tet=False,
+                                                               u_box=True)
+    errs = [rel_l2(out["u_box"][b].cpu().numpy(), ref[b]) for b in range(3)]
+    say(f"  iters {out['iters'].tolist()} errs {[f'{e:.2e}' for e in errs]}")
+    assert max(errs) <= bar
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-10), ("mixed", 1e-7)])
 def test_box16_single_sample(torch_cuda, prec, bar):
     """16^3 box, one noise vector (seed 0), rotated 6,000-tet mesh of [0.2,0.8]^3."""
     torch = torch_cuda
