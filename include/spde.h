@@ -88,7 +88,8 @@ spde_status spde_setup_box(int n, double kappa, double g, spde_handle* out);
 spde_status spde_configure(spde_handle h, spde_precision prec, double rtol,
                            int max_iter, int max_batch);
 
-/* Device workspace size in bytes needed by the current configuration. */
+/* Device workspace size in bytes needed by the current configuration.  On a
+ * handle with a bound workspace the query leaves that binding in use. */
 size_t spde_workspace_bytes(spde_handle h);
 
 /* Bind a caller-owned device buffer of at least spde_workspace_bytes() bytes,

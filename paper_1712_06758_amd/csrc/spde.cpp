@@ -104,6 +104,8 @@ struct Ctx {
   void* mge[kMaxLevels] = {};   // level corrections (l >= 1)
   void* mgd[kMaxLevels] = {};   // cell-wise diagonal of S~ per level (shared by the slots)
   void* mgdi[kMaxLevels] = {};  // and its reciprocal
+  void* cinv = nullptr;         // inverse of the 4^3 level's S~ (exact solve of the persistent kernel)
+  bool cinv_dirty = true;       // cinv must be rebuilt before the next solve
   bool mg_cellwise = false;     // the kappa field enters the multigrid (Galerkin coarse kappa^2)
   bool mg_dirty = false;        // the level diagonals must be rebuilt before the next solve
   double* resid_out = nullptr;  // [max_batch]
@@ -176,6 +178,10 @@ void set_level(Level& L, int m, double kappa) {
   L.dgi = nullptr;
 }
 
+// The persistent kernel solves the 4^3 level exactly when its top level is
+// 4^3 or larger.
+bool coarse_dense(const Ctx* c) { return c->lv[c->top].m >= 4; }
+
 size_t coarse_bytes(const Ctx* c, int top) {
   size_t tot = 0;
   for (int l = top; l < c->nlev; ++l) tot += 4 * (size_t)c->lv[l].nc * c->szm();
@@ -186,6 +192,7 @@ void plan_hierarchy(Ctx* c) {
   c->nlev = 0;
   for (int m = c->n; m >= 1; m >>= 1) set_level(c->lv[c->nlev++], m, c->kappa_pre);
   c->mg_dirty = c->mg_cellwise;   // level diagonals (if any) are rebuilt before the next solve
+  c->cinv_dirty = true;
   // persistent kernel: the largest levels (below the finest) that fit in LDS, at most 16^3
   int top = c->nlev - 1;
   for (int l = 1; l < c->nlev; ++l) {
@@ -232,6 +239,9 @@ size_t layout(Ctx* c, char* base) {
     c->mgd[l] = take(c->lv[l].nc * c->szm());
     c->mgdi[l] = take(c->lv[l].nc * c->szm());
   }
+  c->cinv = take((size_t)64 * 64 * c->szm());
+  c->cp.cinv = c->cinv;
+  if (base) c->cinv_dirty = true;   // new memory: the inverse is built again
   c->F.part_up = (double*)take(B * (size_t)c->nb_up0 * 2 * 8);
   c->F.part_pb = (double*)take(B * (size_t)c->nb_pb * 2 * 8);
   c->F.sc = (Scalars*)take(B * sizeof(Scalars));
@@ -362,6 +372,8 @@ spde_status enqueue_vcycle(Ctx* c, const View& V, int batch, hipStream_t st, int
     Timed t(c, KID_MG_DOWN, iter, st, l, s0, batch);
     HIPCHK(launch_mg_down(f64, eff_down(c, l), false, V.mgb[l], V.mgb[l], V.mgb[l + 1], c->lv[l], batch, sc, st));
   }
+  if (c->cinv_dirty && coarse_dense(c))
+    return fail(SPDE_EINVAL, "the exact 4^3 coarse solve was not prepared before the V-cycle");
   {
     Timed t(c, KID_MG_COARSE, iter, st, 0, s0, batch);
     HIPCHK(launch_mg_coarse(f64, V.mgb[c->top], V.mge[c->top], c->cp, c->coarse_lds, batch, sc, st));
@@ -675,7 +687,7 @@ spde_status autotune(Ctx* c, hipStream_t st) {
 // Gershgorin bound (k2 + 12 a) / (k2 + 6 a) of D^-1 S~ is largest where k2 is
 // smallest, and every level's k2 is at least kappa_min^2 H^3).  The float64
 // chain is built in a Lanczos buffer that no solve uses between calls.
-spde_status prepare_mg_coeffs(Ctx* c, hipStream_t st) {
+spde_status prepare_mg_diag(Ctx* c, hipStream_t st) {
   if (!c->mg_dirty) return SPDE_OK;
   if (!c->mg_cellwise || !c->box.kap) { c->mg_dirty = false; return SPDE_OK; }
   const int64_t nc = c->box.nc;
@@ -712,7 +724,26 @@ spde_status prepare_mg_coeffs(Ctx* c, hipStream_t st) {
   for (int l = c->top; l < c->nlev; ++l) c->cp.lv[l - c->top] = c->lv[l];
   c->kappa_pre = kmin;
   c->mg_dirty = false;
+  c->cinv_dirty = true;
   drop_graphs(c);
+  return SPDE_OK;
+}
+
+// The multigrid coefficients of the next solve: the level diagonals (cell-wise
+// kappa) and the inverse of the 4^3 level's operator, both on the stream.
+spde_status prepare_mg_coeffs(Ctx* c, hipStream_t st) {
+  spde_status s = prepare_mg_diag(c, st);
+  if (s != SPDE_OK) return s;
+  if (c->cinv_dirty) {
+    if (coarse_dense(c)) {
+      int l4 = -1;
+      for (int l = c->top; l < c->nlev; ++l)
+        if (c->lv[l].m == 4) l4 = l;
+      if (l4 < 0 || !c->cinv) return fail(SPDE_EINVAL, "no 4^3 level for the exact coarse solve");
+      HIPCHK(launch_coarse_inverse(c->fp64(), c->lv[l4], c->cinv, st));
+    }
+    c->cinv_dirty = false;
+  }
   return SPDE_OK;
 }
 
@@ -791,13 +822,41 @@ spde_status spde_set_coefficients(spde_handle h, const double* kappa_dev, const 
   // new level coefficients of the preconditioner; shapes, tiles and layout stay
   for (int l = 0; l < c->nlev; ++l) set_level(c->lv[l], c->lv[l].m, c->kappa_pre);
   for (int l = c->top; l < c->nlev; ++l) c->cp.lv[l - c->top] = c->lv[l];
+  c->cinv_dirty = true;
   return SPDE_OK;
+}
+
+// Bytes the layout needs, leaving the handle's bound pointers as they are
+// (a size-only layout sets every pointer it lays out to null).
+size_t workspace_size(Ctx* c) {
+  const Fields F = c->F;
+  void* mgb[kMaxLevels];
+  void* mge[kMaxLevels];
+  void* mgd[kMaxLevels];
+  void* mgdi[kMaxLevels];
+  std::copy(c->mgb, c->mgb + kMaxLevels, mgb);
+  std::copy(c->mge, c->mge + kMaxLevels, mge);
+  std::copy(c->mgd, c->mgd + kMaxLevels, mgd);
+  std::copy(c->mgdi, c->mgdi + kMaxLevels, mgdi);
+  void* cinv = c->cinv;
+  const void* cp_cinv = c->cp.cinv;
+  double* resid_out = c->resid_out;
+  const size_t need = layout(c, nullptr);
+  c->F = F;
+  std::copy(mgb, mgb + kMaxLevels, c->mgb);
+  std::copy(mge, mge + kMaxLevels, c->mge);
+  std::copy(mgd, mgd + kMaxLevels, c->mgd);
+  std::copy(mgdi, mgdi + kMaxLevels, c->mgdi);
+  c->cinv = cinv;
+  c->cp.cinv = cp_cinv;
+  c->resid_out = resid_out;
+  return need;
 }
 
 size_t spde_workspace_bytes(spde_handle h) {
   Ctx* c = reinterpret_cast<Ctx*>(h);
   if (!c || !c->configured) return 0;
-  return layout(c, nullptr);
+  return workspace_size(c);
 }
 
 spde_status spde_bind_workspace(spde_handle h, void* dev_ptr, size_t bytes) {
@@ -827,7 +886,7 @@ spde_status spde_bind_workspace(spde_handle h, void* dev_ptr, size_t bytes) {
   }
   drop_graphs(c);
   plan_hierarchy(c);
-  const size_t need = layout(c, nullptr);
+  const size_t need = workspace_size(c);
   if (bytes < need) return fail(SPDE_ENOMEM, "workspace has %zu bytes, %zu needed", bytes, need);
   layout(c, (char*)dev_ptr);
   c->ws = (char*)dev_ptr;

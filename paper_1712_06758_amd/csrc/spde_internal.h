@@ -144,6 +144,8 @@ struct CoarseParams {
   int nl;                      // levels handled (top first, last is 1^3 or the coarsest)
   Level lv[kMaxLevels];
   int64_t off[kMaxLevels];     // element offset of each level's 4 arrays in LDS
+  const void* cinv;            // 64 x 64 inverse of the 4^3 level's operator (level precision),
+                               // row-major; read when the top level is 4^3 or larger
 };
 
 // Device pointers of the MINRES state.  Index [p] is the buffer parity.
@@ -214,12 +216,15 @@ hipError_t prepare_coarse(bool fp64, size_t lds_bytes);
                                  hipStream_t st);                                                             \
   hipError_t prepare_coarse_##NAME(size_t lds_bytes);                                                         \
   hipError_t launch_mg_coarse_##NAME(const void* btop, void* etop, const CoarseParams& P, size_t lds_bytes,   \
-                                     int batch, const Scalars* sc, hipStream_t st);
+                                     int batch, const Scalars* sc, hipStream_t st);                          \
+  hipError_t launch_coarse_inverse_##NAME(const Level& L, void* out, hipStream_t st);
 SPDE_MG_DECL(f32)
 SPDE_MG_DECL(f64)
 #undef SPDE_MG_DECL
 hipError_t launch_mg_coarse(bool fp64, const void* btop, void* etop, const CoarseParams& P, size_t lds_bytes,
                             int batch, const Scalars* sc, hipStream_t st);
+// Inverse of the 4^3 level's operator S~ (L.m must be 4) into out (64 x 64, level precision).
+hipError_t launch_coarse_inverse(bool fp64, const Level& L, void* out, hipStream_t st);
 hipError_t launch_scalar(const Fields& F, int nb_up, int nb_pb, int batch, hipStream_t st);
 hipError_t launch_operator(bool z_fp64, const Fields& F, const Box& bx, int batch, hipStream_t st);
 hipError_t launch_fix_solution(const Fields& F, const Box& bx, int batch, int slot0, hipStream_t st);

@@ -347,6 +347,22 @@ def test_recorded_tiles_reproduce_a_sample_bitwise(torch_cuda, prec):
     assert a["iters"].tolist() == b["iters"].tolist()
 
 
+def test_workspace_size_query_after_binding_keeps_the_handle(torch_cuda):
+    """Asking a bound handle for its workspace size lays the workspace out
+    without touching the bound pointers: the next call gives the same samples."""
+    torch = torch_cuda
+    from paper_1712_06758_amd import _abi
+    n = 32
+    say(f"workspace size query after binding n={n}")
+    xi = torch.tensor(xi_batch(n, [7, 8]), device="cuda")
+    box = P().Box(n, 20.0, 3.0, precision="mixed", max_batch=2)
+    a = box.sample(xi, u_tet=False, u_box=True)
+    assert _abi.lib().spde_workspace_bytes(box._hh.h) > 0
+    b = box.sample(xi, u_tet=False, u_box=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a["u_box"], b["u_box"])
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_streaming_operator_pass_gives_the_same_samples(torch_cuda, prec):
     """A launch whose vectors exceed the last-level cache streams them through
