@@ -112,6 +112,26 @@ def _run_sample(torch, n, kappa, prec, xi, mesh=None, **kw):
     return box, out
 
 
+@pytest.mark.parametrize("prec,bar,max_iters", [("fp64", 1e-10, 50), ("mixed", 1e-7, 38)])
+@pytest.mark.parametrize("n", [32, 64])
+def test_small_kappa_every_sample(torch_cuda, prec, bar, max_iters, n):
+    """kappa = 0.5: the reaction term is small on every level, so the coarse
+    levels (down to the exact 4^3 solve) carry the diffusion.  Every sample
+    meets the bar and the iterations stay those of kappa = 20 (36 / 47)."""
+    torch = torch_cuda
+    kappa = 0.5
+    g = gval(kappa)
+    xi = xi_batch(n, [1, 2])
+    ref = oracle_u(n, kappa, g, xi)
+    say(f"small kappa {prec} n={n}")
+    out = P().Box(n, kappa, g, precision=prec, max_batch=2).sample(torch.tensor(xi, device="cuda"), u_tet=False,
+                                                                   u_box=True)
+    errs = [rel_l2(out["u_box"][b].cpu().numpy(), ref[b]) for b in range(2)]
+    say(f"  iters {out['iters'].tolist()} errs {[f'{e:.2e}' for e in errs]}")
+    assert max(errs) <= bar
+    assert int(out["iters"].max()) <= max_iters
+
+
 @pytest.mark.parametrize("prec,bar", [("fp64", 1e-10), ("mixed", 1e-7)])
 @pytest.mark.parametrize("n", [4, 8])
 def test_small_boxes_every_sample(torch_cuda, prec, bar, n):
